@@ -1,0 +1,516 @@
+/*
+ * CPU oracle for the prism gravity / gravity-gradient forward operator.
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library; the product path never does.  It
+ * shares no code with the HIP implementation.
+ *
+ * What it computes is the plain definition of the operator:
+ *
+ *   d_c(p,q) = sum_{l,m,n} G_c[(p,q),(l,m,n)] rho(l,m,n)      (eq. 3 / eq. 4)
+ *
+ * where G_c is the exact volume integral of the point-source kernel over the
+ * right rectangular prism of cell (l,m,n), for component c.  Evaluation is in
+ * x87 extended precision (long double, 64-bit mantissa): the closed forms below
+ * are differences of eight corner terms that grow with distance while the
+ * result shrinks, so plain double loses up to ~1e-10 relative on the deep
+ * layers of a 1024^2 grid; extended precision keeps the oracle ~2000x below
+ * that.
+ *
+ * Conventions (the paper leaves them implicit, section 2.1):
+ *   - z points down; the model top is z = 0; the station plane is z = -h.
+ *   - Cell (l,m,n) spans x in [l dx,(l+1)dx], y in [m dy,(m+1)dy],
+ *     z in [n dz,(n+1)dz]; station (p,q) sits at ((p+1/2)dx, (q+1/2)dy, -h),
+ *     one above each surface cell (section 2.1: N_d = nx*ny).
+ *   - Relative coordinates are source minus station, so z > 0 inside cells.
+ *   - U = G rho \iiint dV / r;  g = grad U (pointing at the mass, gz > 0 for
+ *     a positive mass below);  T_ab = d^2 U / da db.
+ *   - Component order: gz, gxx, gxy, gxz, gyy, gyz, gzz.
+ *   - G = 6.672e-11 N m^2 / kg^2, the constant printed with eq. 2.
+ *
+ * Closed forms, with corners (x_i, y_j, z_k), i,j,k in {lower, upper}, and
+ * sign mu = +1 when an odd number of the three coordinates are upper bounds
+ * (the inclusion-exclusion of a triple definite integral; eq. 2's
+ * mu_ijk = (-1)^(i+j+k) with 1-based bounds):
+ *   gz  = -G rho sum mu [ x asinh(y/sqrt(x^2+z^2)) + y asinh(x/sqrt(y^2+z^2))
+ *                         - z atan(x y / (z r)) ]                    (eq. 2)
+ *   gxx = -G rho sum mu atan2(y z, x r)
+ *   gyy = -G rho sum mu atan2(x z, y r)
+ *   gzz = -G rho sum mu atan(x y / (z r))
+ *   gxy =  G rho sum mu ln(z + r)
+ *   gxz =  G rho sum mu asinh(y / sqrt(x^2+z^2))
+ *   gyz =  G rho sum mu asinh(x / sqrt(y^2+z^2))
+ * The tensor forms follow from integrating (3 a b - r^2 delta_ab) / r^5 one
+ * axis at a time; eq. 2 reads ln(y/sqrt(x^2+z^2) + sqrt(1 + y^2/(x^2+z^2))),
+ * which is asinh(y/sqrt(x^2+z^2)) and is evaluated as such (the form
+ * ln(y + r) cancels catastrophically for y < 0).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef long double ld;
+
+enum { C_GZ = 0, C_GXX = 1, C_GXY = 2, C_GXZ = 3, C_GYY = 4, C_GYZ = 5, C_GZZ = 6, NCOMP = 7 };
+
+static const ld GRAV = 6.672e-11L; /* eq. 2 */
+
+int orc_ncomp(void) { return NCOMP; }
+double orc_grav_const(void) { return (double)GRAV; }
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------------------------------ */
+/* Corner terms of the closed forms (without G rho and without mu).          */
+/* ------------------------------------------------------------------------ */
+static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
+{
+    ld x2 = x * x, y2 = y * y, z2 = z * z;
+    ld r = sqrtl(x2 + y2 + z2);
+    ld sxz = sqrtl(x2 + z2);
+    ld syz = sqrtl(y2 + z2);
+    ld ash_y = asinhl(y / sxz);        /* = ln(y + r) - ln sqrt(x^2+z^2) */
+    ld ash_x = asinhl(x / syz);        /* = ln(x + r) - ln sqrt(y^2+z^2) */
+    ld at_z = atanl((x * y) / (z * r));
+    f[C_GZ] = -(x * ash_y + y * ash_x - z * at_z);
+    f[C_GXX] = -atan2l(y * z, x * r);
+    f[C_GYY] = -atan2l(x * z, y * r);
+    f[C_GZZ] = -at_z;
+    f[C_GXY] = logl(z + r);
+    f[C_GXZ] = ash_y;
+    f[C_GYZ] = ash_x;
+}
+
+/* mu for corner (i,j,k), each 0 = lower bound, 1 = upper bound. */
+static ld corner_sign(int i, int j, int k) { return ((i + j + k) & 1) ? 1.0L : -1.0L; }
+
+/* Kernel of one prism (per unit density, G included) from its corners. */
+static void prism_ld(ld x1, ld x2, ld y1, ld y2, ld z1, ld z2, ld out[NCOMP])
+{
+    ld xs[2] = {x1, x2}, ys[2] = {y1, y2}, zs[2] = {z1, z2};
+    ld acc[NCOMP] = {0};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) {
+                ld f[NCOMP];
+                corner_terms(xs[i], ys[j], zs[k], f);
+                ld mu = corner_sign(i, j, k);
+                for (int c = 0; c < NCOMP; ++c) acc[c] += mu * f[c];
+            }
+    for (int c = 0; c < NCOMP; ++c) out[c] = GRAV * acc[c];
+}
+
+/* Public: one prism given by its bounds relative to the station
+ * (source minus station, z down, z1 < z2, z1 > 0).  out[7] in SI per kg/m^3. */
+void orc_prism(double x1, double x2, double y1, double y2, double z1, double z2, double out[NCOMP])
+{
+    ld o[NCOMP];
+    prism_ld(x1, x2, y1, y2, z1, z2, o);
+    for (int c = 0; c < NCOMP; ++c) out[c] = (double)o[c];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre brute force of the point-source kernel.                    */
+/* ------------------------------------------------------------------------ */
+
+/* Nodes and weights on [-1,1]: Newton iteration on P_n from the Chebyshev
+ * guess cos(pi (i+3/4)/(n+1/2)), using the three-term recurrence. */
+static void gl_rule(int n, ld *x, ld *w)
+{
+    const ld PI = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        ld t = cosl(PI * (i + 0.75L) / (n + 0.5L));
+        ld dp = 1;
+        for (int it = 0; it < 100; ++it) {
+            ld p0 = 1, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                ld p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            /* p1 = P_n(t), p0 = P_{n-1}(t) */
+            dp = n * (t * p1 - p0) / (t * t - 1);
+            ld dt = p1 / dp;
+            t -= dt;
+            if (fabsl(dt) < 1e-19L) break;
+        }
+        {
+            ld p0 = 1, p1 = t;
+            for (int k = 2; k <= n; ++k) {
+                ld p2 = ((2 * k - 1) * t * p1 - (k - 1) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (t * p1 - p0) / (t * t - 1);
+        }
+        x[i] = t;
+        w[i] = 2 / ((1 - t * t) * dp * dp);
+    }
+}
+
+/* Point-source kernel at relative position (x,y,z) of a unit mass, G included:
+ * gz = G z / r^3, T_ab = G (3 a b - r^2 delta_ab) / r^5. */
+static void point_kernel(ld x, ld y, ld z, ld k[NCOMP])
+{
+    ld r2 = x * x + y * y + z * z;
+    ld r = sqrtl(r2);
+    ld ir3 = 1 / (r2 * r);
+    ld ir5 = ir3 / r2;
+    k[C_GZ] = GRAV * z * ir3;
+    k[C_GXX] = GRAV * (3 * x * x - r2) * ir5;
+    k[C_GYY] = GRAV * (3 * y * y - r2) * ir5;
+    k[C_GZZ] = GRAV * (3 * z * z - r2) * ir5;
+    k[C_GXY] = GRAV * 3 * x * y * ir5;
+    k[C_GXZ] = GRAV * 3 * x * z * ir5;
+    k[C_GYZ] = GRAV * 3 * y * z * ir5;
+}
+
+#define GL_MAX 32
+
+static void gl_box(ld x1, ld x2, ld y1, ld y2, ld z1, ld z2, int n, const ld *gx, const ld *gw,
+                   ld acc[NCOMP])
+{
+    ld cx = (x1 + x2) / 2, hx = (x2 - x1) / 2;
+    ld cy = (y1 + y2) / 2, hy = (y2 - y1) / 2;
+    ld cz = (z1 + z2) / 2, hz = (z2 - z1) / 2;
+    ld s[NCOMP] = {0};
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int k = 0; k < n; ++k) {
+                ld kk[NCOMP];
+                point_kernel(cx + hx * gx[i], cy + hy * gx[j], cz + hz * gx[k], kk);
+                ld w = gw[i] * gw[j] * gw[k];
+                for (int c = 0; c < NCOMP; ++c) s[c] += w * kk[c];
+            }
+    for (int c = 0; c < NCOMP; ++c) acc[c] += s[c] * hx * hy * hz;
+}
+
+static void gl_adaptive(ld x1, ld x2, ld y1, ld y2, ld z1, ld z2, ld ratio, int n, const ld *gx,
+                        const ld *gw, int depth, ld acc[NCOMP])
+{
+    ld cx = (x1 + x2) / 2, cy = (y1 + y2) / 2, cz = (z1 + z2) / 2;
+    ld hd = sqrtl((x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1) + (z2 - z1) * (z2 - z1)) / 2;
+    ld dist = sqrtl(cx * cx + cy * cy + cz * cz);
+    if (hd <= ratio * dist || depth >= 24) {
+        gl_box(x1, x2, y1, y2, z1, z2, n, gx, gw, acc);
+        return;
+    }
+    ld xb[3] = {x1, cx, x2}, yb[3] = {y1, cy, y2}, zb[3] = {z1, cz, z2};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k)
+                gl_adaptive(xb[i], xb[i + 1], yb[j], yb[j + 1], zb[k], zb[k + 1], ratio, n, gx, gw,
+                            depth + 1, acc);
+}
+
+/* Public: adaptive tensor Gauss-Legendre integral of the point kernel over a
+ * prism (relative bounds as in orc_prism).  Boxes are halved along every axis
+ * until half-diagonal / centre distance <= ratio, then integrated with an
+ * order^3 rule.  Returns 0, or -1 for a bad order. */
+int orc_prism_gl(double x1, double x2, double y1, double y2, double z1, double z2, double ratio,
+                 int order, double out[NCOMP])
+{
+    if (order < 1 || order > GL_MAX || !(ratio > 0)) return -1;
+    ld gx[GL_MAX], gw[GL_MAX];
+    gl_rule(order, gx, gw);
+    ld acc[NCOMP] = {0};
+    gl_adaptive(x1, x2, y1, y2, z1, z2, ratio, order, gx, gw, 0, acc);
+    for (int c = 0; c < NCOMP; ++c) out[c] = (double)acc[c];
+    return 0;
+}
+
+/* Public: the rule itself, for tests (nodes on [-1,1]). */
+int orc_gl_rule(int order, double *x, double *w)
+{
+    if (order < 1 || order > GL_MAX) return -1;
+    ld gx[GL_MAX], gw[GL_MAX];
+    gl_rule(order, gx, gw);
+    for (int i = 0; i < order; ++i) {
+        x[i] = (double)gx[i];
+        w[i] = (double)gw[i];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Kernel by offset (translation equivalence, eq. 7 / eq. 10).               */
+/* ------------------------------------------------------------------------ */
+
+/* Bounds of the cell at offset (a, b) = (l - p, m - q) in layer n, relative
+ * to its station. */
+static void cell_bounds(int a, int b, int n, double dx, double dy, double dz, double h, ld bx[6])
+{
+    bx[0] = ((ld)a - 0.5L) * dx;
+    bx[1] = ((ld)a + 0.5L) * dx;
+    bx[2] = ((ld)b - 0.5L) * dy;
+    bx[3] = ((ld)b + 0.5L) * dy;
+    bx[4] = (ld)h + (ld)n * dz;
+    bx[5] = (ld)h + (ld)(n + 1) * dz;
+}
+
+/* Public: kernel values of cells given by offsets (a[i], b[i]) in layer n.
+ * mode 0: closed form for every entry.
+ * mode 1: closed form when the station-to-cell-centre distance is below 24
+ *         half-diagonals, otherwise one 8^3 Gauss-Legendre rule over the cell
+ *         (at that distance its truncation error is far below long-double
+ *         rounding, while the closed form starts to lose digits).
+ * out[count][7]. */
+int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int count, const int *a,
+                       const int *b, int mode, double *out)
+{
+    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0) || n < 0 || count < 0) return -1;
+    ld gx[GL_MAX], gw[GL_MAX];
+    gl_rule(8, gx, gw);
+    ld hd = sqrtl((ld)dx * dx + (ld)dy * dy + (ld)dz * dz) / 2;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int i = 0; i < count; ++i) {
+        ld bx[6], o[NCOMP];
+        cell_bounds(a[i], b[i], n, dx, dy, dz, h, bx);
+        ld cx = (bx[0] + bx[1]) / 2, cy = (bx[2] + bx[3]) / 2, cz = (bx[4] + bx[5]) / 2;
+        ld dist = sqrtl(cx * cx + cy * cy + cz * cz);
+        if (mode == 1 && dist >= 24 * hd) {
+            for (int c = 0; c < NCOMP; ++c) o[c] = 0;
+            gl_box(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], 8, gx, gw, o);
+        } else {
+            prism_ld(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], o);
+        }
+        for (int c = 0; c < NCOMP; ++c) out[(size_t)i * NCOMP + c] = (double)o[c];
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Node planes: corner terms on a plane of grid nodes, reused by the cells   */
+/* that share them (each cell still sums its own eight corners).             */
+/* ------------------------------------------------------------------------ */
+
+/* Fill plane[(jy*(nxn) + ix)*7 + c] with corner_terms at x = (v0 + ix - 1/2) dx,
+ * y = (w0 + jy - 1/2) dy, depth z. */
+static void fill_plane(ld *plane, int v0, int nxn, int w0, int nyn, double dx, double dy, ld z)
+{
+    for (int jy = 0; jy < nyn; ++jy) {
+        ld y = ((ld)(w0 + jy) - 0.5L) * dy;
+        for (int ix = 0; ix < nxn; ++ix) {
+            ld x = ((ld)(v0 + ix) - 0.5L) * dx;
+            corner_terms(x, y, z, plane + ((size_t)jy * nxn + ix) * NCOMP);
+        }
+    }
+}
+
+/* K_c of the cell whose lower-x node is ix, lower-y node jy, between planes
+ * lo (z1) and hi (z2): the eight-corner sum, G included. */
+static inline void cell_from_planes(const ld *lo, const ld *hi, int nxn, int ix, int jy,
+                                    ld out[NCOMP])
+{
+    const ld *pl[2] = {lo, hi};
+    ld acc[NCOMP] = {0};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int k = 0; k < 2; ++k) {
+                const ld *f = pl[k] + ((size_t)(jy + j) * nxn + (ix + i)) * NCOMP;
+                ld mu = corner_sign(i, j, k);
+                for (int c = 0; c < NCOMP; ++c) acc[c] += mu * f[c];
+            }
+    for (int c = 0; c < NCOMP; ++c) out[c] = GRAV * acc[c];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct forward sum (eq. 3) at chosen stations.                            */
+/* ------------------------------------------------------------------------ */
+
+/* rho[nb][nz][ny][nx] (kg/m^3).  Stations (sp[s], sq[s]).  out[nb][nst][7].
+ * Work is split over (station, layer); per-layer partial sums are reduced in
+ * layer order, so the result does not depend on the thread count. */
+int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
+                const double *rho, int nst, const int *sp, const int *sq, double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nb < 1 || nst < 0) return -1;
+    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    for (int s = 0; s < nst; ++s)
+        if (sp[s] < 0 || sp[s] >= nx || sq[s] < 0 || sq[s] >= ny) return -1;
+    size_t nxn = (size_t)nx + 1, nyn = (size_t)ny + 1;
+    size_t plane_sz = nxn * nyn * NCOMP;
+    size_t nitems = (size_t)nst * nz;
+    ld *part = (ld *)calloc(nitems * nb * NCOMP + 1, sizeof(ld));
+    if (!part) return -2;
+    int err = 0;
+#pragma omp parallel
+    {
+        ld *lo = (ld *)malloc(plane_sz * sizeof(ld));
+        ld *hi = (ld *)malloc(plane_sz * sizeof(ld));
+        if (!lo || !hi) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (long it = 0; it < (long)nitems; ++it) {
+            if (!lo || !hi) continue;
+            int s = (int)(it / nz), n = (int)(it % nz);
+            int p = sp[s], q = sq[s];
+            /* offsets a = l - p, l in [0,nx): x nodes (a - 1/2) dx for a in [-p, nx - p]. */
+            fill_plane(lo, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)n * dz);
+            fill_plane(hi, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)(n + 1) * dz);
+            ld *dst = part + (size_t)it * nb * NCOMP;
+            for (int m = 0; m < ny; ++m)
+                for (int l = 0; l < nx; ++l) {
+                    ld k[NCOMP];
+                    cell_from_planes(lo, hi, (int)nxn, l, m, k);
+                    for (int b = 0; b < nb; ++b) {
+                        ld r = rho[(((size_t)b * nz + n) * ny + m) * nx + l];
+                        for (int c = 0; c < NCOMP; ++c) dst[b * NCOMP + c] += k[c] * r;
+                    }
+                }
+        }
+        free(lo);
+        free(hi);
+    }
+    if (err) {
+        free(part);
+        return err;
+    }
+    for (int b = 0; b < nb; ++b)
+        for (int s = 0; s < nst; ++s)
+            for (int c = 0; c < NCOMP; ++c) {
+                ld acc = 0;
+                for (int n = 0; n < nz; ++n) acc += part[(((size_t)s * nz + n) * nb + b) * NCOMP + c];
+                out[((size_t)b * nst + s) * NCOMP + c] = (double)acc;
+            }
+    free(part);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct adjoint sum: g(l,m,n) = sum_c sum_{p,q} G_c[(p,q),(l,m,n)] r_c(p,q) */
+/* ------------------------------------------------------------------------ */
+
+/* r[nb][7][ny][nx] indexed by component slot (unused slots may hold anything,
+ * only comps in mask are read).  Cells (cl, cm, cn).  out[nb][ncell]. */
+int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
+                unsigned mask, const double *r, int ncell, const int *cl, const int *cm,
+                const int *cn, double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nb < 1 || ncell < 0) return -1;
+    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    for (int i = 0; i < ncell; ++i)
+        if (cl[i] < 0 || cl[i] >= nx || cm[i] < 0 || cm[i] >= ny || cn[i] < 0 || cn[i] >= nz)
+            return -1;
+    size_t nxn = (size_t)nx + 1, nyn = (size_t)ny + 1;
+    size_t plane_sz = nxn * nyn * NCOMP;
+    int err = 0;
+#pragma omp parallel
+    {
+        ld *lo = (ld *)malloc(plane_sz * sizeof(ld));
+        ld *hi = (ld *)malloc(plane_sz * sizeof(ld));
+        if (!lo || !hi) {
+#pragma omp atomic write
+            err = -2;
+        }
+#pragma omp for schedule(dynamic, 1)
+        for (int i = 0; i < ncell; ++i) {
+            if (!lo || !hi) continue;
+            int l = cl[i], m = cm[i], n = cn[i];
+            /* a = l - p for p in [0,nx): a in [l-nx+1, l]; x nodes v in [l-nx+1, l+1]. */
+            int v0 = l - nx + 1, w0 = m - ny + 1;
+            fill_plane(lo, v0, (int)nxn, w0, (int)nyn, dx, dy, (ld)h + (ld)n * dz);
+            fill_plane(hi, v0, (int)nxn, w0, (int)nyn, dx, dy, (ld)h + (ld)(n + 1) * dz);
+            for (int b = 0; b < nb; ++b) {
+                ld acc = 0;
+                for (int q = 0; q < ny; ++q)
+                    for (int p = 0; p < nx; ++p) {
+                        ld k[NCOMP];
+                        cell_from_planes(lo, hi, (int)nxn, (l - p) - v0, (m - q) - w0, k);
+                        for (int c = 0; c < NCOMP; ++c)
+                            if (mask & (1u << c))
+                                acc += k[c] * r[(((size_t)b * NCOMP + c) * ny + q) * nx + p];
+                    }
+                out[(size_t)b * ncell + i] = (double)acc;
+            }
+        }
+        free(lo);
+        free(hi);
+    }
+    return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Dense kernel matrix for tiny grids (the point-element method, eq. 12).    */
+/* ------------------------------------------------------------------------ */
+
+/* out[Nd][Nm] for component comp; station i = p + q nx, cell
+ * j = l + m nx + n nx ny (section 2.2's numbering, x fastest).  Every entry
+ * is evaluated from the absolute positions of its own station and cell. */
+int orc_dense_matrix(int nx, int ny, int nz, double dx, double dy, double dz, double h, int comp,
+                     double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || comp < 0 || comp >= NCOMP) return -1;
+    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    long nd = (long)nx * ny, nm = (long)nx * ny * nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long i = 0; i < nd; ++i) {
+        int p = (int)(i % nx), q = (int)(i / nx);
+        ld sx = ((ld)p + 0.5L) * dx, sy = ((ld)q + 0.5L) * dy, sz = -(ld)h;
+        for (long j = 0; j < nm; ++j) {
+            int l = (int)(j % nx), m = (int)((j / nx) % ny), n = (int)(j / ((long)nx * ny));
+            ld o[NCOMP];
+            prism_ld((ld)l * dx - sx, (ld)(l + 1) * dx - sx, (ld)m * dy - sy, (ld)(m + 1) * dy - sy,
+                     (ld)n * dz - sz, (ld)(n + 1) * dz - sz, o);
+            out[i * nm + j] = (double)o[comp];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Uniform blocks evaluated as single merged prisms (superposition).         */
+/* ------------------------------------------------------------------------ */
+
+/* Blocks k: cells l in [blk[6k],blk[6k+1]), m in [blk[6k+2],blk[6k+3]),
+ * n in [blk[6k+4],blk[6k+5]) with density val[k].  Since the closed form
+ * integrates any box, a block needs one evaluation per station instead of one
+ * per cell.  out[nst][7] = sum_k val[k] * K(block k). */
+int orc_blocks_at_stations(int nx, int ny, int nz, double dx, double dy, double dz, double h,
+                           int nblk, const int *blk, const double *val, int nst, const int *sp,
+                           const int *sq, double *out)
+{
+    if (nx < 1 || ny < 1 || nz < 1 || nblk < 0 || nst < 0) return -1;
+    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    for (int k = 0; k < nblk; ++k) {
+        const int *B = blk + 6 * k;
+        if (B[0] < 0 || B[1] > nx || B[0] >= B[1] || B[2] < 0 || B[3] > ny || B[2] >= B[3] ||
+            B[4] < 0 || B[5] > nz || B[4] >= B[5])
+            return -1;
+    }
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int s = 0; s < nst; ++s) {
+        ld sx = ((ld)sp[s] + 0.5L) * dx, sy = ((ld)sq[s] + 0.5L) * dy, sz = -(ld)h;
+        ld acc[NCOMP] = {0};
+        for (int k = 0; k < nblk; ++k) {
+            const int *B = blk + 6 * k;
+            ld o[NCOMP];
+            prism_ld((ld)B[0] * dx - sx, (ld)B[1] * dx - sx, (ld)B[2] * dy - sy, (ld)B[3] * dy - sy,
+                     (ld)B[4] * dz - sz, (ld)B[5] * dz - sz, o);
+            for (int c = 0; c < NCOMP; ++c) acc[c] += (ld)val[k] * o[c];
+        }
+        for (int c = 0; c < NCOMP; ++c) out[(size_t)s * NCOMP + c] = (double)acc[c];
+    }
+    return 0;
+}
