@@ -1,0 +1,260 @@
+"""Benchmark of the fast gravity / gravity-gradient forward operator.
+
+Workload: the paper-scale grid, nx = ny = 1024, nz = 100, 20 m cubic cells,
+stations 10 m above the top, all six components (gz, gxx, gxy, gxz, gyy, gyz);
+density = 20 seeded random prisms plus a Gaussian random field.  A step is
+one forward apply d = G rho with the kernel spectra resident in HBM and the
+density already on the device; the plan (kernel table + spectra) is built
+once before the timed region and its time is reported as ``plan_ms``.
+
+Metric: effective kernel evaluations per second, B * C * N_d * N_m / t,
+the number of kernel-matrix entries the operator applies per second
+(C = 6 components, N_d = nx*ny stations, N_m = nx*ny*nz cells).
+
+One JSON line is printed.  Besides the headline FP64 forward it carries the
+FP32 path, the adjoint, a live roofline of the dominant kernel (the column
+pass), the CPU oracle timed on a bounded sample, and (with --serve-seconds)
+a short served-latency run.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "effective N_d·N_m kernel-evals/s at 1024²×100 6-comp; p50/p99 served latency"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_colpass_paper_scale.json")
+KERNEL_SOURCES = ["colpass.hip", "gf_fft.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2005_10160_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def colpass_algorithmic_bytes(p, B):
+    """Bytes the forward column pass must move per launch: every resident
+    spectrum value once, the row-transformed density columns once, and the
+    per-split partial data spectra once (quarter-plane spectra, one real per
+    frequency; complex intermediates)."""
+    info = p.info
+    s = 8 if p.precision == "f64" else 4
+    U = info.px // 2 + 1
+    Q = info.py // 2 + 1
+    spectra = info.n_spec * info.nz * U * Q * s
+    R = B * info.nz * U * info.ny * 2 * s
+    ws = p.workspace_bytes("forward", B)
+    S = round((ws // (2 * s * U * info.ny) - B * info.nz) / (B * info.n_spec))
+    D = S * B * info.n_spec * U * info.ny * 2 * s
+    return spectra + R + D, S
+
+
+def time_forward(p, rho, d, ws, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        p.forward(rho, d, ws)
+    torch.cuda.synchronize()
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        starts[i].record()
+        p.forward(rho, d, ws)
+        ends[i].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    return per, wall
+
+
+def time_passes(p, rho, d, ws, steps, op="forward"):
+    """Per-pass durations from HIP events recorded by the library on the
+    launch stream around each pass."""
+    import torch
+    p.set_timing(True)
+    out = []
+    for _ in range(steps):
+        if op == "forward":
+            p.forward(rho, d, ws)
+        else:
+            p.adjoint(d, rho, ws)
+        out.append(p.last_pass_ms(op))
+    p.set_timing(False)
+    torch.cuda.synchronize()
+    return np.array(out)
+
+
+def cpu_baseline(g, rho_np, n_stations, threads):
+    import oracle
+    if threads:
+        oracle.set_threads(threads)
+    from synth import sample_stations
+    st = sample_stations(g.nx, g.ny, 0, seed=1)[[8, 0, 3, 5]][:n_stations]
+    t0 = time.perf_counter()
+    oracle.forward(g, rho_np, st)
+    dt = time.perf_counter() - t0
+    evals = len(st) * g.nm * 6
+    return {
+        "value": evals / dt,
+        "unit": "kernel-evals/s",
+        "cores": oracle.max_threads(),
+        "kind": "oracle",
+        "sample": "long-double direct sum (eq. 3) of the same 1024^2x100 model at %d station(s), "
+                  "all %d cells, 6 components counted; %.1f s wall" % (len(st), g.nm, dt),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32 side run")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-stations", type=int, default=2)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=0.0)
+    ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the operator runs on a single MI355X and has no "
+              "multi-GPU path in this build (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2005_10160_amd as gf
+    from synth import PRESETS, prisms_and_grf
+
+    g = PRESETS["medium" if args.small else "paper_scale"]
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("bench: generating density %dx%dx%d" % (g.nx, g.ny, g.nz))
+    rho_np = prisms_and_grf(g.nx, g.ny, g.nz, 20 if not args.small else 6, 302, 303)
+
+    def run(prec, steps, warmup, with_adjoint):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        log("bench: plan %s" % prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, gf.ALL6, prec, device=dev)
+        plan_wall = (time.perf_counter() - t0) * 1e3
+        rho = torch.from_numpy(rho_np).to(dev, dt)
+        d = torch.empty((1, 6, g.ny, g.nx), dtype=dt, device=dev)
+        wsb = max(p.workspace_bytes("forward", 1), p.workspace_bytes("adjoint", 1))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        log("bench: timing %s forward" % prec)
+        per, wall = time_forward(p, rho.unsqueeze(0), d, ws, steps, warmup)
+        passes = time_passes(p, rho.unsqueeze(0), d, ws, steps)
+        res = {"plan": p, "per": per, "wall": wall, "passes": passes, "plan_ms": plan_wall,
+               "spectra_bytes": p.spectra_bytes, "ws_bytes": wsb}
+        if with_adjoint:
+            log("bench: timing %s adjoint" % prec)
+            g_out = torch.empty((1, g.nz, g.ny, g.nx), dtype=dt, device=dev)
+            for _ in range(warmup):
+                p.adjoint(d, g_out, ws)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                p.adjoint(d, g_out, ws)
+            torch.cuda.synchronize()
+            res["adjoint_ms"] = (time.perf_counter() - t0) * 1e3 / steps
+            res["adjoint_passes"] = time_passes(p, g_out, d, ws, steps, "adjoint")
+        return res
+
+    evals = 6.0 * g.nd * g.nm
+    main_res = run(args.precision, args.steps, args.warmup, not args.no_adjoint)
+    per = main_res["per"]
+    total_ms = sum(per)
+    ms_per_step = total_ms / len(per)
+    value = evals / (ms_per_step * 1e-3)
+
+    p = main_res["plan"]
+    alg_bytes, S = colpass_algorithmic_bytes(p, 1)
+    col_ms = float(np.mean(main_res["passes"][:, 1]))
+    achieved = alg_bytes / (col_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE) and not args.small:
+        try:
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("kernel_hash") == kernel_hash() and tr.get("precision") == args.precision:
+                traffic = tr.get("bytes_per_launch")
+        except Exception:
+            traffic = None
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": "col_forward_kernel (FFT along y + layer reduction + inverse FFT)",
+                "algorithmic_bytes_per_launch": alg_bytes, "layer_splits": S,
+                "kernel_ms": round(col_ms, 4)}
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "kernel-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "%s forward, %dx%dx%d, %gx%gx%g m cells, h=%g m, 6 components, batch 1"
+                               % ("medium" if args.small else "paper-scale", g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h),
+                   "nx": g.nx, "ny": g.ny, "nz": g.nz, "components": 6, "batch": 1,
+                   "precision": args.precision},
+        "roofline": roofline,
+        "median_ms": statistics.median(per),
+        "plan_ms": round(main_res["plan_ms"], 1),
+        "spectra_bytes": main_res["spectra_bytes"],
+        "pass_ms": [round(float(x), 4) for x in main_res["passes"].mean(axis=0)],
+    }
+    if "adjoint_ms" in main_res:
+        line["adjoint_ms_per_step"] = main_res["adjoint_ms"]
+        line["adjoint_pass_ms"] = [round(float(x), 4) for x in main_res["adjoint_passes"].mean(axis=0)]
+    p.close()
+    del main_res
+
+    if not args.no_f32 and args.precision == "f64":
+        r32 = run("f32", args.steps, args.warmup, False)
+        ms32 = sum(r32["per"]) / len(r32["per"])
+        a32, _ = colpass_algorithmic_bytes(r32["plan"], 1)
+        c32 = float(np.mean(r32["passes"][:, 1]))
+        line["f32"] = {"value": evals / (ms32 * 1e-3), "ms_per_step": ms32,
+                       "pass_ms": [round(float(x), 4) for x in r32["passes"].mean(axis=0)],
+                       "colpass_GBs": round(a32 / (c32 * 1e-3) / 1e9, 1), "plan_ms": round(r32["plan_ms"], 1)}
+        r32["plan"].close()
+        del r32
+
+    if args.serve_seconds > 0:
+        from paper_2005_10160_amd import serve
+        line["served"] = serve.bench_served(args.serve_seconds)
+
+    if not args.no_cpu:
+        log("bench: CPU oracle baseline")
+        line["cpu_baseline"] = cpu_baseline(g, rho_np, args.cpu_stations, args.cpu_threads)
+
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

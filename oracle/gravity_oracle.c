@@ -338,8 +338,10 @@ static inline void cell_from_planes(const ld *lo, const ld *hi, int nxn, int ix,
 /* ------------------------------------------------------------------------ */
 
 /* rho[nb][nz][ny][nx] (kg/m^3).  Stations (sp[s], sq[s]).  out[nb][nst][7].
- * Work is split over (station, layer); per-layer partial sums are reduced in
- * layer order, so the result does not depend on the thread count. */
+ * Work is split over (station, chunk of consecutive layers), so each node
+ * plane is evaluated once per chunk; partial sums are kept per layer and
+ * reduced in layer order, so the result does not depend on the thread count
+ * or the chunking. */
 int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
                 const double *rho, int nst, const int *sp, const int *sq, double *out)
 {
@@ -349,8 +351,15 @@ int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double 
         if (sp[s] < 0 || sp[s] >= nx || sq[s] < 0 || sq[s] >= ny) return -1;
     size_t nxn = (size_t)nx + 1, nyn = (size_t)ny + 1;
     size_t plane_sz = nxn * nyn * NCOMP;
-    size_t nitems = (size_t)nst * nz;
-    ld *part = (ld *)calloc(nitems * nb * NCOMP + 1, sizeof(ld));
+    /* chunks per station: enough items to keep every thread busy */
+    int nthr = orc_max_threads();
+    int nchunk = (4 * nthr + nst - 1) / (nst > 0 ? nst : 1);
+    if (nchunk < 1) nchunk = 1;
+    if (nchunk > nz) nchunk = nz;
+    int clen = (nz + nchunk - 1) / nchunk;
+    nchunk = (nz + clen - 1) / clen;
+    size_t nitems = (size_t)nst * nchunk;
+    ld *part = (ld *)calloc((size_t)nst * nz * nb * NCOMP + 1, sizeof(ld));
     if (!part) return -2;
     int err = 0;
 #pragma omp parallel
@@ -364,21 +373,27 @@ int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double 
 #pragma omp for schedule(dynamic, 1)
         for (long it = 0; it < (long)nitems; ++it) {
             if (!lo || !hi) continue;
-            int s = (int)(it / nz), n = (int)(it % nz);
+            int s = (int)(it / nchunk), ch = (int)(it % nchunk);
             int p = sp[s], q = sq[s];
+            int n0 = ch * clen, n1 = n0 + clen < nz ? n0 + clen : nz;
             /* offsets a = l - p, l in [0,nx): x nodes (a - 1/2) dx for a in [-p, nx - p]. */
-            fill_plane(lo, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)n * dz);
-            fill_plane(hi, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)(n + 1) * dz);
-            ld *dst = part + (size_t)it * nb * NCOMP;
-            for (int m = 0; m < ny; ++m)
-                for (int l = 0; l < nx; ++l) {
-                    ld k[NCOMP];
-                    cell_from_planes(lo, hi, (int)nxn, l, m, k);
-                    for (int b = 0; b < nb; ++b) {
-                        ld r = rho[(((size_t)b * nz + n) * ny + m) * nx + l];
-                        for (int c = 0; c < NCOMP; ++c) dst[b * NCOMP + c] += k[c] * r;
+            fill_plane(lo, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)n0 * dz);
+            for (int n = n0; n < n1; ++n) {
+                fill_plane(hi, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)(n + 1) * dz);
+                ld *dst = part + ((size_t)s * nz + n) * nb * NCOMP;
+                for (int m = 0; m < ny; ++m)
+                    for (int l = 0; l < nx; ++l) {
+                        ld k[NCOMP];
+                        cell_from_planes(lo, hi, (int)nxn, l, m, k);
+                        for (int b = 0; b < nb; ++b) {
+                            ld r = rho[(((size_t)b * nz + n) * ny + m) * nx + l];
+                            for (int c = 0; c < NCOMP; ++c) dst[b * NCOMP + c] += k[c] * r;
+                        }
                     }
-                }
+                ld *tmp = lo;
+                lo = hi;
+                hi = tmp;
+            }
         }
         free(lo);
         free(hi);

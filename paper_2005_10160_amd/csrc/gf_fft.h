@@ -1,0 +1,211 @@
+// Device building blocks: complex arithmetic, small DFTs and a workgroup
+// Stockham FFT whose data live in registers between LDS exchanges.
+//
+// The FFTs implement the discrete Fourier transforms that diagonalise the
+// circulant embedding of each BTTB layer block (section 2.2.3, eq. 18):
+// forward X[k] = sum_j x[j] exp(-2 pi i j k / N), inverse with exp(+...),
+// both unnormalised.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace gf {
+
+template <typename T>
+struct __attribute__((aligned(2 * sizeof(T)))) cx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cx<T> mk(T re, T im) { return cx<T>{re, im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> add(cx<T> a, cx<T> b) { return cx<T>{a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> sub(cx<T> a, cx<T> b) { return cx<T>{a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cx<T> mul(cx<T> a, cx<T> b)
+{
+    return cx<T>{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> scale(cx<T> a, T s) { return cx<T>{a.re * s, a.im * s}; }
+template <typename T>
+__device__ __forceinline__ cx<T> conjg(cx<T> a) { return cx<T>{a.re, -a.im}; }
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> rot(cx<T> a)
+{
+    return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
+}
+
+template <int X>
+struct ilog2 {
+    static constexpr int value = 1 + ilog2<X / 2>::value;
+};
+template <>
+struct ilog2<1> {
+    static constexpr int value = 0;
+};
+
+// ---------------------------------------------------------------- DFTs ----
+template <typename T, int R, bool INV>
+struct dft;
+
+template <typename T, bool INV>
+struct dft<T, 1, INV> {
+    __device__ __forceinline__ static void run(cx<T> *) {}
+};
+
+template <typename T, bool INV>
+struct dft<T, 2, INV> {
+    __device__ __forceinline__ static void run(cx<T> *a)
+    {
+        cx<T> t = a[0];
+        a[0] = add(t, a[1]);
+        a[1] = sub(t, a[1]);
+    }
+};
+
+template <typename T, bool INV>
+struct dft<T, 4, INV> {
+    __device__ __forceinline__ static void run(cx<T> *a)
+    {
+        cx<T> t0 = add(a[0], a[2]);
+        cx<T> t1 = sub(a[0], a[2]);
+        cx<T> t2 = add(a[1], a[3]);
+        cx<T> t3 = rot<T, INV>(sub(a[1], a[3]));
+        a[0] = add(t0, t2);
+        a[2] = sub(t0, t2);
+        a[1] = add(t1, t3);
+        a[3] = sub(t1, t3);
+    }
+};
+
+template <typename T, bool INV>
+struct dft<T, 8, INV> {
+    __device__ __forceinline__ static void run(cx<T> *a)
+    {
+        const T h = T(0.70710678118654752440084436210484903928);
+        cx<T> e[4] = {a[0], a[2], a[4], a[6]};
+        cx<T> o[4] = {a[1], a[3], a[5], a[7]};
+        dft<T, 4, INV>::run(e);
+        dft<T, 4, INV>::run(o);
+        // o[k] *= w8^k, w8 = exp(-+ i pi / 4)
+        cx<T> o1 = INV ? cx<T>{(o[1].re - o[1].im) * h, (o[1].re + o[1].im) * h}
+                       : cx<T>{(o[1].re + o[1].im) * h, (o[1].im - o[1].re) * h};
+        cx<T> o2 = rot<T, INV>(o[2]);
+        cx<T> o3 = INV ? cx<T>{-(o[3].re + o[3].im) * h, (o[3].re - o[3].im) * h}
+                       : cx<T>{(o[3].im - o[3].re) * h, -(o[3].re + o[3].im) * h};
+        a[0] = add(e[0], o[0]);
+        a[4] = sub(e[0], o[0]);
+        a[1] = add(e[1], o1);
+        a[5] = sub(e[1], o1);
+        a[2] = add(e[2], o2);
+        a[6] = sub(e[2], o2);
+        a[3] = add(e[3], o3);
+        a[7] = sub(e[3], o3);
+    }
+};
+
+// ------------------------------------------------------------ twiddles ----
+// tw[m] = exp(-2 pi i m / TL) for m in [0, TL), TL = 2^twlog (a power of two
+// no smaller than any transform length in use).  W(a, L) = exp(-+2 pi i a / L).
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog, int a, int logL)
+{
+    cx<T> w = tw[a << (twlog - logL)];
+    return INV ? conjg(w) : w;
+}
+
+// ------------------------------------------------------ workgroup FFT ----
+// One length-N transform per group of NT threads; PPT = N/NT points per
+// thread.  Stockham autosort: stage s with radix R and span Ns combines
+// elements j + k N/R (k < R) of butterfly j after twiddling by
+// W((j mod Ns) k, Ns R) and writes them to (j div Ns) Ns R + (j mod Ns) + k Ns.
+// Register slot v[m R + k] of thread t holds element t + NT (m + k PPT/R);
+// with R = PPT this is element t + NT k.  The same layout holds on output
+// (with the radix of the last stage), so callers index slots through
+// elem_in()/elem_out().  LDS: two arrays (re, im) of lds_words() entries per
+// group, padded by one word every R to spread banks.
+template <typename T, int N, int NT, int R>
+struct BlockFFT {
+    static constexpr int PPT = N / NT;
+    static constexpr int LOGN = ilog2<N>::value;
+    static constexpr int LOGR = ilog2<R>::value;
+    static_assert(N % NT == 0, "N must be a multiple of NT");
+    static_assert(PPT % R == 0, "PPT must be a multiple of R");
+    static constexpr int LAST_R = (LOGN % LOGR == 0) ? R : (1 << (LOGN % LOGR));
+    static constexpr int NSTAGES = (LOGN + LOGR - 1) / LOGR;
+
+    __host__ __device__ static constexpr int lds_words() { return N + N / R + 1; }
+    __device__ __forceinline__ static int pad(int i) { return i + (i >> LOGR); }
+
+    // element index (multiplier of NT plus t) held by register slot s, for a
+    // stage of radix RR
+    __host__ __device__ static constexpr int slot_elem(int s, int RR)
+    {
+        return (s / RR) + (s % RR) * (PPT / RR);
+    }
+    __host__ __device__ static constexpr int first_r() { return N >= R ? R : N; }
+    // element multiplier of slot s on input / output
+    __host__ __device__ static constexpr int elem_in(int s) { return slot_elem(s, first_r()); }
+    __host__ __device__ static constexpr int elem_out(int s) { return slot_elem(s, LAST_R); }
+
+    template <int Ns, bool INV>
+    __device__ __forceinline__ static void stage(cx<T> (&v)[PPT], T *sre, T *sim, int t,
+                                                 const cx<T> *__restrict__ tw, int twlog)
+    {
+        constexpr int RS = (Ns * R <= N) ? R : (N / Ns);
+        constexpr int NB = PPT / RS;
+        constexpr int LOGL = ilog2<Ns * RS>::value;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            const int j = t + m * NT;
+            const int jm = j & (Ns - 1);
+            if (Ns > 1) {
+#pragma unroll
+                for (int k = 1; k < RS; ++k)
+                    v[m * RS + k] = mul(v[m * RS + k], twiddle<T, INV>(tw, twlog, jm * k, LOGL));
+            }
+            dft<T, RS, INV>::run(&v[m * RS]);
+        }
+        if constexpr (Ns * RS < N) {
+            constexpr int NS2 = Ns * RS;
+            constexpr int R2 = (NS2 * R <= N) ? R : (N / NS2);
+            constexpr int NB2 = PPT / R2;
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                const int j = t + m * NT;
+                const int jm = j & (Ns - 1);
+                const int base = (j >> ilog2<Ns>::value) * Ns * RS + jm;
+#pragma unroll
+                for (int k = 0; k < RS; ++k) {
+                    const int idx = pad(base + k * Ns);
+                    sre[idx] = v[m * RS + k].re;
+                    sim[idx] = v[m * RS + k].im;
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int m = 0; m < NB2; ++m)
+#pragma unroll
+                for (int k = 0; k < R2; ++k) {
+                    const int idx = pad(t + m * NT + k * (N / R2));
+                    v[m * R2 + k] = cx<T>{sre[idx], sim[idx]};
+                }
+            stage<NS2, INV>(v, sre, sim, t, tw, twlog);
+        }
+    }
+
+    // Transform in place.  All threads of the workgroup must call it (it
+    // contains workgroup barriers); sre/sim point to this group's LDS area.
+    template <bool INV>
+    __device__ __forceinline__ static void run(cx<T> (&v)[PPT], T *sre, T *sim, int t,
+                                               const cx<T> *__restrict__ tw, int twlog)
+    {
+        stage<1, INV>(v, sre, sim, t, tw, twlog);
+    }
+};
+
+}  // namespace gf

@@ -1,0 +1,80 @@
+// Host-side launchers of the HIP kernels, shared by the plan code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace gf {
+
+// How a slab of rows is formed from source slabs: slab s of batch item b is
+// sum_i w[s][i] * src_slab(b, src[s][i]).  identity: slab s reads source s.
+struct RowCombo {
+    int identity;
+    int nterm[8];
+    int src[8][2];
+    double w[8][2];
+};
+
+// Gauss-Legendre rules on [-1,1] of orders 6, 4 and 3 (in that order).
+struct GLRules {
+    double x[13];
+    double w[13];
+};
+
+struct KgenGeom {
+    int nx, ny, px, py;
+    double dx, dy, dz, h;
+    double t_analytic;   // closed form below this many half-diagonals
+    double t_gl6;        // 6^3 rule below this, 4^3 below t_gl4, 3^3 beyond
+    double t_gl4;
+};
+
+// Forward row transform (real rows of length <= px -> px/2+1 column units,
+// written transposed as out[slab][u][row]).
+//   in       base of source rows; row (b, src, y) at in + ((b*src_per_b + src)*rows + y)*row_len
+//   lin      nonzero entries per row (<= px); the rest of each row is zero
+//   rows     rows per slab; nsub slabs per batch item; nbatch items
+int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int rows, int nsub,
+                   int src_per_b, int nbatch, const RowCombo &cmb, void *out, const void *tw,
+                   int twlog, hipStream_t st);
+
+// Inverse row transform: X(b,o,y)[u] = sum_split sum_i w[o][i] D[split][b][src[o][i]][u][y],
+// then real rows of length px, of which the first nx_out are written, times
+// `scale`, to out[b][o][y][x].
+int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nsplit, int nsrc,
+                   int rows, int nsub, int nbatch, const RowCombo &cmb, void *out, int nx_out,
+                   double scale, const void *tw, int twlog, hipStream_t st);
+
+// Column pass of the forward operator: per column unit u and model b, for
+// each layer n of the split: FFT along y, multiply by conj(K^_{c,n}) and
+// accumulate over n; then inverse FFT per component.
+int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
+                       int U, int ny, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
+
+// Column pass of the adjoint: FFT of the Cs residual columns, then per layer
+// sum_c K^_{c,n} r^_c and an inverse FFT.
+int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
+                       int nz, int U, int ny, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
+
+// Plan time: column FFT of the row-transformed kernel fields and extraction
+// of the quarter-plane spectrum into spec[Cs][nz][U][py/2+1] (float or double).
+int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,
+                    int nz, int U, unsigned imag_mask, const void *tw, int twlog, hipStream_t st);
+
+// Plan time: kernel table of layers [n0, n0+nl) for the Cs components in
+// codes[], written into zeroed circulant fields E[nl][Cs][py][px] (double).
+int launch_kgen_field(void *E, int nl, int n0, int Cs, const int *codes, const KgenGeom &g,
+                      const GLRules &gl, hipStream_t st);
+
+// Upper bound of concurrently resident workgroups of the forward column pass
+// (for choosing the layer split).
+int col_forward_capacity(bool fp64, int py, int Cs, int B);
+int col_forward_groups(bool fp64, int py);
+
+// Largest dynamic LDS allocation a workgroup may request on the current
+// device (bytes).
+size_t lds_limit();
+
+}  // namespace gf

@@ -1,0 +1,643 @@
+// C-ABI of the fast gravity / gravity-gradient forward operator: plan
+// creation (kernel table + resident spectra), forward and adjoint calls.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "gf_launch.h"
+#include "gravfft.h"
+
+namespace {
+
+constexpr double kGrav = 6.672e-11;  // gravitational constant printed with eq. 2
+constexpr int kMaxN = 2048;          // largest nx, ny (Px, Py <= 4096)
+
+thread_local std::string g_err;
+
+gf_status fail(gf_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+int next_pow2(long v)
+{
+    int p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+int log2i(int v)
+{
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+// Gauss-Legendre nodes and weights on [-1,1] (Newton iteration on the
+// Legendre polynomial from the usual cosine initial guess).
+void gauss_legendre(int n, double *x, double *w)
+{
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int i = 0; i < n; ++i) {
+        long double z = cosl(pi * (i + 0.75L) / (n + 0.5L));
+        long double dp = 0;
+        for (int iter = 0; iter < 100; ++iter) {
+            long double p_prev = 1, p = z;
+            for (int k = 2; k <= n; ++k) {
+                long double pn = ((2 * k - 1) * z * p - (k - 1) * p_prev) / k;
+                p_prev = p;
+                p = pn;
+            }
+            dp = n * (z * p - p_prev) / (z * z - 1);
+            long double step = p / dp;
+            z -= step;
+            if (fabsl(step) < 1e-19L) break;
+        }
+        long double p_prev = 1, p = z;
+        for (int k = 2; k <= n; ++k) {
+            long double pn = ((2 * k - 1) * z * p - (k - 1) * p_prev) / k;
+            p_prev = p;
+            p = pn;
+        }
+        dp = n * (z * p - p_prev) / (z * z - 1);
+        x[i] = (double)z;
+        w[i] = (double)(2 / ((1 - z * z) * dp * dp));
+    }
+}
+
+gf::GLRules make_rules()
+{
+    gf::GLRules r{};
+    gauss_legendre(6, r.x, r.w);
+    gauss_legendre(4, r.x + 6, r.w + 6);
+    gauss_legendre(3, r.x + 10, r.w + 10);
+    return r;
+}
+
+// component codes: 0 gz, 1 gxx, 2 gxy, 3 gxz, 4 gyy, 5 gyz, 6 gzz
+bool is_imag(int code) { return code == 3 || code == 5; }   // odd in exactly one of x, y
+bool is_yodd(int code) { return code == 2 || code == 5; }   // odd in y
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p) (void)hipFree(p);
+    }
+};
+
+}  // namespace
+
+struct gf_plan {
+    int nx, ny, nz;
+    double dx, dy, dz, h;
+    unsigned mask;
+    int prec;
+    int max_batch;
+    int px, py, M, U, Q, twlog;
+    int n_out;
+    int out_codes[7];
+    int n_spec;
+    int spec_codes[6];
+    unsigned spec_mask;
+    unsigned imag_mask, yodd_mask;  // over spectral slots
+    gf::RowCombo out_combo;         // output o from spectral slots
+    gf::RowCombo in_combo;          // adjoint: spectral slot s from input components
+    void *spec = nullptr;
+    size_t spec_bytes = 0;
+    void *tw = nullptr;             // twiddles in the plan precision
+    void *tw64 = nullptr;           // twiddles in double (plan-time transforms)
+    void *iws = nullptr;
+    size_t iws_bytes = 0;
+    int device = 0;
+    double plan_ms = 0;
+    bool timing = false;
+    hipEvent_t ev[2][4] = {{nullptr, nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr, nullptr}};
+    bool ev_recorded[2] = {false, false};
+
+    bool fp64() const { return prec == GF_F64; }
+    size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
+    size_t celem() const { return 2 * elem(); }
+    int slot_of(int code) const
+    {
+        for (int s = 0; s < n_spec; ++s)
+            if (spec_codes[s] == code) return s;
+        return -1;
+    }
+    int out_of(int code) const
+    {
+        for (int o = 0; o < n_out; ++o)
+            if (out_codes[o] == code) return o;
+        return -1;
+    }
+    // Layer split of the forward column pass, and layers per split.  Chosen
+    // for one model and used for every batch size, so that a model's result
+    // does not depend on the batch it is computed in.
+    void fwd_split(int /*B*/, int *S, int *lps) const
+    {
+        const int G = gf::col_forward_groups(fp64(), py);
+        const long nblk = ((long)U + G - 1) / G;
+        const int cap = gf::col_forward_capacity(fp64(), py, n_spec, 1);
+        // cost in units of one layer of one round of resident workgroups;
+        // each split adds a partial-sum write and read (~beta layers)
+        const double per_layer = (double)n_spec * Q + 2.0 * ny;
+        const double beta = 4.0 * n_spec * ny / per_layer;
+        int best = 1;
+        double best_cost = 1e300;
+        for (int s = 1; s <= nz && s <= 32; ++s) {
+            const long l = (nz + s - 1) / s;
+            if ((long)(s - 1) * l >= nz) continue;  // empty split
+            const double rounds = std::ceil((double)nblk * s / cap);
+            const double cost = rounds * l + beta * s * (double)nblk / cap;
+            if (cost < best_cost * 0.999) {
+                best_cost = cost;
+                best = s;
+            }
+        }
+        *S = best;
+        *lps = (nz + best - 1) / best;
+    }
+    void adj_split(int B, int *S, int *lps) const
+    {
+        const int G = gf::col_forward_groups(fp64(), py);
+        const long nblk = ((long)U * B + G - 1) / G;
+        const int cap = gf::col_forward_capacity(fp64(), py, n_spec, B);
+        long s = (2L * cap + nblk - 1) / nblk;
+        if (s < 1) s = 1;
+        if (s > nz) s = nz;
+        long l = (nz + s - 1) / s;
+        s = (nz + l - 1) / l;
+        *S = (int)s;
+        *lps = (int)l;
+    }
+    size_t ws_bytes(int op, int B) const
+    {
+        if (op == GF_OP_FORWARD) {
+            int S, l;
+            fwd_split(B, &S, &l);
+            return celem() * (size_t)U * ny * ((size_t)B * nz + (size_t)S * B * n_spec);
+        }
+        return celem() * (size_t)U * ny * ((size_t)B * n_spec + (size_t)B * nz);
+    }
+};
+
+namespace {
+
+gf_status hip_check(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return GF_OK;
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation)
+        return fail(GF_ENOMEM, "%s: %s", what, hipGetErrorString(e));
+    return fail(GF_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <typename T>
+std::vector<T> twiddle_table(int n)
+{
+    std::vector<T> v(2 * (size_t)n);
+    const long double pi = 3.141592653589793238462643383279502884L;
+    for (int m = 0; m < n; ++m) {
+        const long double a = -2 * pi * (long double)m / (long double)n;
+        v[2 * (size_t)m] = (T)cosl(a);
+        v[2 * (size_t)m + 1] = (T)sinl(a);
+    }
+    return v;
+}
+
+gf::KgenGeom kgen_geom(const gf_plan *p)
+{
+    gf::KgenGeom g{};
+    g.nx = p->nx;
+    g.ny = p->ny;
+    g.px = p->px;
+    g.py = p->py;
+    g.dx = p->dx;
+    g.dy = p->dy;
+    g.dz = p->dz;
+    g.h = p->h;
+    g.t_analytic = 8.0;
+    g.t_gl6 = 24.0;
+    g.t_gl4 = 80.0;
+    return g;
+}
+
+gf_status build_spectra(gf_plan *p, hipStream_t st)
+{
+    const size_t field = (size_t)p->py * p->px;
+    const size_t per_pair = field * sizeof(double) + (size_t)p->U * p->py * 2 * sizeof(double);
+    const size_t budget = (size_t)2 << 30;
+    int nl = (int)(budget / (per_pair * p->n_spec));
+    if (nl < 1) nl = 1;
+    if (nl > p->nz) nl = p->nz;
+    DevBuf E, Rk;
+    gf_status s;
+    if ((s = hip_check(hipMalloc(&E.p, field * sizeof(double) * nl * p->n_spec), "kernel field")) != GF_OK)
+        return s;
+    if ((s = hip_check(hipMalloc(&Rk.p, (size_t)p->U * p->py * 2 * sizeof(double) * nl * p->n_spec),
+                       "kernel row spectra")) != GF_OK)
+        return s;
+    const gf::KgenGeom g = kgen_geom(p);
+    const gf::GLRules gl = make_rules();
+    gf::RowCombo ident{};
+    ident.identity = 1;
+    for (int n0 = 0; n0 < p->nz; n0 += nl) {
+        const int nlc = std::min(nl, p->nz - n0);
+        const int npair = nlc * p->n_spec;
+        if ((s = hip_check(hipMemsetAsync(E.p, 0, field * sizeof(double) * npair, st), "memset")) != GF_OK)
+            return s;
+        if (gf::launch_kgen_field(E.p, nlc, n0, p->n_spec, p->spec_codes, g, gl, st) != 0)
+            return fail(GF_EDEVICE, "kernel table launch failed");
+        if (gf::launch_row_r2c(true, p->px, E.p, p->px, p->px, p->py, npair, npair, 1, ident, Rk.p,
+                               p->tw64, p->twlog, st) != 0)
+            return fail(GF_EDEVICE, "kernel row transform launch failed");
+        if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec, nlc, n0, p->n_spec, p->nz, p->U,
+                                p->imag_mask, p->tw64, p->twlog, st) != 0)
+            return fail(GF_EDEVICE, "kernel column transform launch failed");
+    }
+    return hip_check(hipStreamSynchronize(st), "plan synchronise");
+}
+
+void mark(gf_plan *p, int op, int i, hipStream_t st)
+{
+    if (!p->timing) return;
+    (void)hipEventRecord(p->ev[op][i], st);
+    if (i == 3) p->ev_recorded[op] = true;
+}
+
+void free_plan(gf_plan *p)
+{
+    if (!p) return;
+    for (int o = 0; o < 2; ++o)
+        for (int i = 0; i < 4; ++i)
+            if (p->ev[o][i]) (void)hipEventDestroy(p->ev[o][i]);
+    if (p->spec) (void)hipFree(p->spec);
+    if (p->tw) (void)hipFree(p->tw);
+    if (p->tw64 && p->tw64 != p->tw) (void)hipFree(p->tw64);
+    if (p->iws) (void)hipFree(p->iws);
+    delete p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *gf_status_string(gf_status s)
+{
+    switch (s) {
+    case GF_OK: return "GF_OK";
+    case GF_EINVAL: return "GF_EINVAL";
+    case GF_ENOMEM: return "GF_ENOMEM";
+    case GF_EDEVICE: return "GF_EDEVICE";
+    case GF_EUNSUPPORTED: return "GF_EUNSUPPORTED";
+    case GF_EBUSY: return "GF_EBUSY";
+    }
+    return "GF_UNKNOWN";
+}
+
+const char *gf_last_error(void) { return g_err.c_str(); }
+
+gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz, double h,
+                         unsigned components, int precision, int max_batch, void *hip_stream,
+                         gf_plan **out)
+{
+    g_err.clear();
+    if (!out) return fail(GF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(GF_EINVAL, "grid sizes must be >= 1 (got %d,%d,%d)", nx, ny, nz);
+    if (nx > kMaxN || ny > kMaxN)
+        return fail(GF_EUNSUPPORTED, "nx, ny must be <= %d (got %d,%d)", kMaxN, nx, ny);
+    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
+        return fail(GF_EINVAL, "cell sizes must be positive and finite");
+    if (!(h > 0) || !std::isfinite(h)) return fail(GF_EINVAL, "station height h must be > 0");
+    if (components == 0 || (components & ~0x7Fu)) return fail(GF_EINVAL, "bad component mask 0x%x", components);
+    if (precision != GF_F64 && precision != GF_F32) return fail(GF_EINVAL, "bad precision %d", precision);
+    if (max_batch < 0) return fail(GF_EINVAL, "max_batch must be >= 0");
+    if ((long)nz * nx * ny > (1L << 31)) return fail(GF_EUNSUPPORTED, "model too large");
+
+    hipStream_t st = (hipStream_t)hip_stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    gf_plan *p = new (std::nothrow) gf_plan();
+    if (!p) return fail(GF_ENOMEM, "host allocation");
+    p->nx = nx;
+    p->ny = ny;
+    p->nz = nz;
+    p->dx = dx;
+    p->dy = dy;
+    p->dz = dz;
+    p->h = h;
+    p->mask = components;
+    p->prec = precision;
+    p->max_batch = max_batch;
+    // circulant sizes: any P >= 2n-1 embeds the Toeplitz levels exactly
+    p->px = std::max(16, next_pow2(2L * nx - 1));
+    p->py = std::max(16, next_pow2(2L * ny - 1));
+    p->M = p->px / 2;
+    p->U = p->M + 1;
+    p->Q = p->py / 2 + 1;
+    p->twlog = log2i(std::max(p->px, p->py));
+    (void)hipGetDevice(&p->device);
+
+    p->n_out = 0;
+    for (int c = 0; c < 7; ++c)
+        if (components & (1u << c)) p->out_codes[p->n_out++] = c;
+    p->spec_mask = components & 0x3Fu;
+    if (components & GF_GZZ) p->spec_mask |= GF_GXX | GF_GYY;
+    p->n_spec = 0;
+    p->imag_mask = p->yodd_mask = 0;
+    for (int c = 0; c < 6; ++c)
+        if (p->spec_mask & (1u << c)) {
+            const int s = p->n_spec++;
+            p->spec_codes[s] = c;
+            if (is_imag(c)) p->imag_mask |= 1u << s;
+            if (is_yodd(c)) p->yodd_mask |= 1u << s;
+        }
+    std::memset(&p->out_combo, 0, sizeof(p->out_combo));
+    for (int o = 0; o < p->n_out; ++o) {
+        const int code = p->out_codes[o];
+        if (code < 6) {
+            p->out_combo.nterm[o] = 1;
+            p->out_combo.src[o][0] = p->slot_of(code);
+            p->out_combo.w[o][0] = 1.0;
+        } else {
+            p->out_combo.nterm[o] = 2;
+            p->out_combo.src[o][0] = p->slot_of(1);
+            p->out_combo.src[o][1] = p->slot_of(4);
+            p->out_combo.w[o][0] = -1.0;
+            p->out_combo.w[o][1] = -1.0;
+        }
+    }
+    std::memset(&p->in_combo, 0, sizeof(p->in_combo));
+    for (int s = 0; s < p->n_spec; ++s) {
+        const int code = p->spec_codes[s];
+        int k = 0;
+        const int o = p->out_of(code);
+        if (o >= 0) {
+            p->in_combo.src[s][k] = o;
+            p->in_combo.w[s][k] = 1.0;
+            ++k;
+        }
+        const int oz = p->out_of(6);
+        if ((code == 1 || code == 4) && oz >= 0) {
+            p->in_combo.src[s][k] = oz;
+            p->in_combo.w[s][k] = -1.0;
+            ++k;
+        }
+        p->in_combo.nterm[s] = k;
+    }
+
+    gf_status s;
+    const int tl = 1 << p->twlog;
+    {
+        auto t64 = twiddle_table<double>(tl);
+        if ((s = hip_check(hipMalloc(&p->tw64, t64.size() * sizeof(double)), "twiddles")) != GF_OK) {
+            free_plan(p);
+            return s;
+        }
+        if ((s = hip_check(hipMemcpy(p->tw64, t64.data(), t64.size() * sizeof(double), hipMemcpyHostToDevice),
+                           "twiddles")) != GF_OK) {
+            free_plan(p);
+            return s;
+        }
+        if (p->fp64()) {
+            p->tw = p->tw64;
+        } else {
+            auto t32 = twiddle_table<float>(tl);
+            if ((s = hip_check(hipMalloc(&p->tw, t32.size() * sizeof(float)), "twiddles")) != GF_OK ||
+                (s = hip_check(hipMemcpy(p->tw, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice),
+                               "twiddles")) != GF_OK) {
+                free_plan(p);
+                return s;
+            }
+        }
+    }
+    p->spec_bytes = (size_t)p->n_spec * nz * p->U * p->Q * p->elem();
+    if ((s = hip_check(hipMalloc(&p->spec, p->spec_bytes), "spectra")) != GF_OK) {
+        free_plan(p);
+        return s;
+    }
+    if ((s = build_spectra(p, st)) != GF_OK) {
+        free_plan(p);
+        return s;
+    }
+    if (max_batch > 0) {
+        p->iws_bytes = std::max(p->ws_bytes(GF_OP_FORWARD, max_batch), p->ws_bytes(GF_OP_ADJOINT, max_batch));
+        if ((s = hip_check(hipMalloc(&p->iws, p->iws_bytes), "internal workspace")) != GF_OK) {
+            free_plan(p);
+            return s;
+        }
+    }
+    p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    *out = p;
+    return GF_OK;
+}
+
+gf_status gf_plan_destroy(gf_plan *plan)
+{
+    free_plan(plan);
+    return GF_OK;
+}
+
+gf_status gf_plan_get_info(const gf_plan *p, gf_plan_info_t *info)
+{
+    if (!p || !info) return fail(GF_EINVAL, "NULL argument");
+    info->nx = p->nx;
+    info->ny = p->ny;
+    info->nz = p->nz;
+    info->px = p->px;
+    info->py = p->py;
+    info->n_out = p->n_out;
+    info->n_spec = p->n_spec;
+    info->components = p->mask;
+    info->spec_mask = p->spec_mask;
+    info->precision = p->prec;
+    info->max_batch = p->max_batch;
+    info->spectra_bytes = p->spec_bytes;
+    info->internal_workspace_bytes = p->iws_bytes;
+    info->plan_ms = p->plan_ms;
+    return GF_OK;
+}
+
+size_t gf_plan_bytes(const gf_plan *p) { return p ? p->spec_bytes : 0; }
+
+gf_status gf_workspace_bytes(const gf_plan *p, int op, int batch, size_t *bytes)
+{
+    if (!p || !bytes) return fail(GF_EINVAL, "NULL argument");
+    if (op != GF_OP_FORWARD && op != GF_OP_ADJOINT) return fail(GF_EINVAL, "bad op %d", op);
+    if (batch < 1) return fail(GF_EINVAL, "batch must be >= 1");
+    *bytes = p->ws_bytes(op, batch);
+    return GF_OK;
+}
+
+static gf_status pick_ws(gf_plan *p, int op, int batch, void *&ws, size_t ws_bytes)
+{
+    const size_t need = p->ws_bytes(op, batch);
+    if (!ws) {
+        if (!p->iws || batch > p->max_batch)
+            return fail(GF_EBUSY, "no workspace given and batch %d exceeds the internal workspace (max_batch %d)",
+                        batch, p->max_batch);
+        ws = p->iws;
+        return GF_OK;
+    }
+    if (ws_bytes < need)
+        return fail(GF_EBUSY, "workspace of %zu bytes is smaller than the %zu bytes needed", ws_bytes, need);
+    return GF_OK;
+}
+
+gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *workspace,
+                     size_t workspace_bytes, void *hip_stream)
+{
+    if (!p || !rho || !d) return fail(GF_EINVAL, "NULL argument");
+    if (batch < 1) return fail(GF_EINVAL, "batch must be >= 1");
+    gf_status s = pick_ws(p, GF_OP_FORWARD, batch, workspace, workspace_bytes);
+    if (s != GF_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int S, lps;
+    p->fwd_split(batch, &S, &lps);
+    char *R = (char *)workspace;
+    char *D = R + p->celem() * (size_t)batch * p->nz * p->U * p->ny;
+    gf::RowCombo ident{};
+    ident.identity = 1;
+    mark(p, GF_OP_FORWARD, 0, st);
+    if (gf::launch_row_r2c(p->fp64(), p->px, rho, p->nx, p->nx, p->ny, p->nz, p->nz, batch, ident, R,
+                           p->tw, p->twlog, st) != 0)
+        return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_FORWARD, 1, st);
+    if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec, D, batch, p->nz, p->U, p->ny, p->n_spec, S, lps,
+                               p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
+        return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_FORWARD, 2, st);
+    const double scale = kGrav / ((double)p->py * p->M);
+    if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->U * p->ny, S, p->n_spec, p->ny,
+                           p->n_out, batch, p->out_combo, d, p->nx, scale, p->tw, p->twlog, st) != 0)
+        return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_FORWARD, 3, st);
+    return GF_OK;
+}
+
+gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *workspace,
+                     size_t workspace_bytes, void *hip_stream)
+{
+    if (!p || !r || !g) return fail(GF_EINVAL, "NULL argument");
+    if (batch < 1) return fail(GF_EINVAL, "batch must be >= 1");
+    gf_status s = pick_ws(p, GF_OP_ADJOINT, batch, workspace, workspace_bytes);
+    if (s != GF_OK) return s;
+    hipStream_t st = (hipStream_t)hip_stream;
+    int S, lps;
+    p->adj_split(batch, &S, &lps);
+    char *R = (char *)workspace;
+    char *Gt = R + p->celem() * (size_t)batch * p->n_spec * p->U * p->ny;
+    mark(p, GF_OP_ADJOINT, 0, st);
+    if (gf::launch_row_r2c(p->fp64(), p->px, r, p->nx, p->nx, p->ny, p->n_spec, p->n_out, batch, p->in_combo,
+                           R, p->tw, p->twlog, st) != 0)
+        return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_ADJOINT, 1, st);
+    if (gf::launch_col_adjoint(p->fp64(), p->py, R, p->spec, Gt, batch, p->nz, p->U, p->ny, p->n_spec, S, lps,
+                               p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
+        return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_ADJOINT, 2, st);
+    gf::RowCombo ident{};
+    ident.identity = 1;
+    const double scale = kGrav / ((double)p->py * p->M);
+    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, 0, 1, p->nz, p->ny, p->nz, batch, ident, g, p->nx, scale,
+                           p->tw, p->twlog, st) != 0)
+        return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_ADJOINT, 3, st);
+    return GF_OK;
+}
+
+gf_status gf_plan_set_timing(gf_plan *p, int enable)
+{
+    if (!p) return fail(GF_EINVAL, "NULL plan");
+    if (enable && !p->ev[0][0]) {
+        for (int o = 0; o < 2; ++o)
+            for (int i = 0; i < 4; ++i) {
+                gf_status s = hip_check(hipEventCreate(&p->ev[o][i]), "event");
+                if (s != GF_OK) return s;
+            }
+    }
+    p->timing = enable != 0;
+    return GF_OK;
+}
+
+gf_status gf_plan_last_pass_ms(gf_plan *p, int op, double ms[3])
+{
+    if (!p || !ms) return fail(GF_EINVAL, "NULL argument");
+    if (op != GF_OP_FORWARD && op != GF_OP_ADJOINT) return fail(GF_EINVAL, "bad op %d", op);
+    if (!p->ev_recorded[op]) return fail(GF_EINVAL, "no timed call of this op yet");
+    gf_status s = hip_check(hipEventSynchronize(p->ev[op][3]), "event sync");
+    if (s != GF_OK) return s;
+    for (int i = 0; i < 3; ++i) {
+        float v = 0;
+        if ((s = hip_check(hipEventElapsedTime(&v, p->ev[op][i], p->ev[op][i + 1]), "elapsed")) != GF_OK) return s;
+        ms[i] = v;
+    }
+    return GF_OK;
+}
+
+gf_status gf_debug_kernel_table(const gf_plan *p, int n, double *host_out)
+{
+    if (!p || !host_out) return fail(GF_EINVAL, "NULL argument");
+    if (n < 0 || n >= p->nz) return fail(GF_EINVAL, "layer %d out of range", n);
+    const size_t field = (size_t)p->py * p->px;
+    DevBuf E;
+    gf_status s;
+    if ((s = hip_check(hipMalloc(&E.p, field * 6 * sizeof(double)), "debug field")) != GF_OK) return s;
+    if ((s = hip_check(hipMemset(E.p, 0, field * 6 * sizeof(double)), "memset")) != GF_OK) return s;
+    const int codes[6] = {0, 1, 2, 3, 4, 5};
+    if (gf::launch_kgen_field(E.p, 1, n, 6, codes, kgen_geom(p), make_rules(), nullptr) != 0)
+        return fail(GF_EDEVICE, "kernel table launch failed");
+    std::vector<double> h(field * 6);
+    if ((s = hip_check(hipMemcpy(h.data(), E.p, h.size() * sizeof(double), hipMemcpyDeviceToHost), "copy")) != GF_OK)
+        return s;
+    const int na = 2 * p->nx - 1, nb = 2 * p->ny - 1;
+    for (int b = -(p->ny - 1); b <= p->ny - 1; ++b)
+        for (int a = -(p->nx - 1); a <= p->nx - 1; ++a) {
+            const size_t src = (size_t)((b + p->py) % p->py) * p->px + (size_t)((a + p->px) % p->px);
+            const size_t dst = (size_t)(b + p->ny - 1) * na + (size_t)(a + p->nx - 1);
+            double v[6];
+            for (int c = 0; c < 6; ++c) v[c] = kGrav * h[(size_t)c * field + src];
+            for (int c = 0; c < 6; ++c) host_out[(size_t)c * na * nb + dst] = v[c];
+            host_out[(size_t)6 * na * nb + dst] = -(v[1] + v[4]);
+        }
+    return GF_OK;
+}
+
+gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double *host_out)
+{
+    if (!p || !host_out) return fail(GF_EINVAL, "NULL argument");
+    if (n < 0 || n >= p->nz) return fail(GF_EINVAL, "layer %d out of range", n);
+    int code = -1;
+    for (int c = 0; c < 6; ++c)
+        if (component == (1u << c)) code = c;
+    const int slot = code >= 0 ? p->slot_of(code) : -1;
+    if (slot < 0) return fail(GF_EINVAL, "component 0x%x has no resident spectrum", component);
+    const size_t cnt = (size_t)p->U * p->Q;
+    const size_t off = ((size_t)slot * p->nz + n) * cnt;
+    gf_status s;
+    if (p->fp64()) {
+        if ((s = hip_check(hipMemcpy(host_out, (const double *)p->spec + off, cnt * sizeof(double),
+                                     hipMemcpyDeviceToHost), "copy")) != GF_OK)
+            return s;
+    } else {
+        std::vector<float> tmp(cnt);
+        if ((s = hip_check(hipMemcpy(tmp.data(), (const float *)p->spec + off, cnt * sizeof(float),
+                                     hipMemcpyDeviceToHost), "copy")) != GF_OK)
+            return s;
+        for (size_t i = 0; i < cnt; ++i) host_out[i] = tmp[i];
+    }
+    return GF_OK;
+}
+
+}  // extern "C"

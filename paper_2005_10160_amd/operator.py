@@ -1,0 +1,226 @@
+"""Python face of the fast gravity / gravity-gradient operator.
+
+``plan(nx, ny, nz, dx, dy, dz, h, components)`` builds the resident kernel
+spectra on the GPU; ``forward(plan, rho, d)`` computes d = G rho (eq. 4) and
+``adjoint(plan, r, g)`` computes g = G^T r.  PyTorch supplies device memory
+and the stream; every arithmetic step runs in ``libgravfft.so``.
+"""
+
+import ctypes
+
+import torch
+
+from . import _native as nat
+
+COMPONENTS = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz")
+GZ, GXX, GXY, GXZ, GYY, GYZ, GZZ = (1 << i for i in range(7))
+ALL6 = 0x3F
+ALL7 = 0x7F
+
+
+def components_mask(components):
+    """Accept a bit mask or an iterable of component names."""
+    if isinstance(components, int):
+        return components
+    m = 0
+    for c in components:
+        m |= 1 << COMPONENTS.index(c)
+    return m
+
+
+def _stream_handle(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Plan:
+    """A geometry's resident kernel spectra (see include/gravfft.h)."""
+
+    def __init__(self, nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64",
+                 max_batch=0, device=None, stream=None):
+        lib = nat.load()
+        device = torch.device("cuda") if device is None else torch.device(device)
+        if device.type != "cuda":
+            raise ValueError("the operator runs on a GPU device, got %s" % device)
+        if device.index is None:
+            device = torch.device("cuda", torch.cuda.current_device())
+        self.device = device
+        prec = {"f64": nat.GF_F64, "fp64": nat.GF_F64, "float64": nat.GF_F64,
+                "f32": nat.GF_F32, "fp32": nat.GF_F32, "float32": nat.GF_F32}[str(precision).lower()]
+        self.precision = "f64" if prec == nat.GF_F64 else "f32"
+        self.dtype = torch.float64 if prec == nat.GF_F64 else torch.float32
+        self.mask = components_mask(components)
+        self.geometry = (int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(h))
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            st = _stream_handle(stream)
+            nat.check(lib.gf_plan_create(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(h),
+                                         ctypes.c_uint(self.mask), prec, int(max_batch), st, ctypes.byref(handle)),
+                      "gf_plan_create")
+        self._h = handle
+        info = nat.PlanInfo()
+        nat.check(lib.gf_plan_get_info(self._h, ctypes.byref(info)), "gf_plan_get_info")
+        self.info = info
+        self.nx, self.ny, self.nz = info.nx, info.ny, info.nz
+        self.n_out = info.n_out
+        self.out_components = tuple(COMPONENTS[i] for i in range(7) if self.mask >> i & 1)
+
+    # -- lifetime ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            nat.load().gf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- facts ----------------------------------------------------------------
+    @property
+    def spectra_bytes(self):
+        return int(self.info.spectra_bytes)
+
+    @property
+    def plan_ms(self):
+        return float(self.info.plan_ms)
+
+    def workspace_bytes(self, op, batch):
+        out = ctypes.c_size_t()
+        opc = nat.GF_OP_FORWARD if op in ("forward", 0) else nat.GF_OP_ADJOINT
+        nat.check(nat.load().gf_workspace_bytes(self._h, opc, int(batch), ctypes.byref(out)), "gf_workspace_bytes")
+        return int(out.value)
+
+    def _workspace(self, op, batch, workspace, stream=None):
+        need = self.workspace_bytes(op, batch)
+        if workspace is None:
+            workspace = torch.empty(need, dtype=torch.uint8, device=self.device)
+        if workspace.device != self.device or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous tensor on %s" % self.device)
+        nbytes = workspace.numel() * workspace.element_size()
+        if stream is not None:
+            # the caching allocator must not hand this memory out before the
+            # kernels on `stream` are done with it
+            workspace.record_stream(stream)
+        return workspace, nbytes
+
+    def _check_in(self, x, shape_tail, name):
+        if not isinstance(x, torch.Tensor) or x.device != self.device:
+            raise ValueError("%s must be a tensor on %s" % (name, self.device))
+        if x.dtype != self.dtype:
+            raise ValueError("%s must be %s for a %s plan" % (name, self.dtype, self.precision))
+        if not x.is_contiguous():
+            raise ValueError("%s must be contiguous" % name)
+        if x.dim() == len(shape_tail):
+            x = x.unsqueeze(0)
+        if tuple(x.shape[1:]) != tuple(shape_tail) or x.dim() != len(shape_tail) + 1:
+            raise ValueError("%s has shape %s, expected [B]+%s" % (name, tuple(x.shape), list(shape_tail)))
+        return x
+
+    # -- operator ----------------------------------------------------------
+    def forward(self, rho, out=None, workspace=None, stream=None):
+        """d = G rho.  rho [B][nz][ny][nx] (or [nz][ny][nx]) -> d [B][C][ny][nx]."""
+        squeeze = rho.dim() == 3
+        rho = self._check_in(rho, (self.nz, self.ny, self.nx), "rho")
+        B = rho.shape[0]
+        if out is None:
+            out = torch.empty((B, self.n_out, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        out = self._check_in(out, (self.n_out, self.ny, self.nx), "d")
+        if out.shape[0] != B:
+            raise ValueError("d batch %d != rho batch %d" % (out.shape[0], B))
+        ws, nb = self._workspace("forward", B, workspace, stream)
+        with torch.cuda.device(self.device):
+            nat.check(nat.load().gf_forward(self._h, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            B, ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream)),
+                      "gf_forward")
+        return out[0] if squeeze else out
+
+    def adjoint(self, r, out=None, workspace=None, stream=None):
+        """g = G^T r.  r [B][C][ny][nx] (or [C][ny][nx]) -> g [B][nz][ny][nx]."""
+        squeeze = r.dim() == 3
+        r = self._check_in(r, (self.n_out, self.ny, self.nx), "r")
+        B = r.shape[0]
+        if out is None:
+            out = torch.empty((B, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        out = self._check_in(out, (self.nz, self.ny, self.nx), "g")
+        if out.shape[0] != B:
+            raise ValueError("g batch %d != r batch %d" % (out.shape[0], B))
+        ws, nb = self._workspace("adjoint", B, workspace, stream)
+        with torch.cuda.device(self.device):
+            nat.check(nat.load().gf_adjoint(self._h, ctypes.c_void_p(r.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                            B, ctypes.c_void_p(ws.data_ptr()), nb, _stream_handle(stream)),
+                      "gf_adjoint")
+        return out[0] if squeeze else out
+
+    # -- timing ----------------------------------------------------------------
+    def set_timing(self, enable=True):
+        nat.check(nat.load().gf_plan_set_timing(self._h, 1 if enable else 0), "gf_plan_set_timing")
+
+    def last_pass_ms(self, op="forward"):
+        """(row transform, column pass, inverse row transform) ms of the last
+        timed call of op."""
+        ms = (ctypes.c_double * 3)()
+        opc = nat.GF_OP_FORWARD if op in ("forward", 0) else nat.GF_OP_ADJOINT
+        nat.check(nat.load().gf_plan_last_pass_ms(self._h, opc, ms), "gf_plan_last_pass_ms")
+        return tuple(ms)
+
+    # -- test access ---------------------------------------------------------
+    def debug_kernel_table(self, n):
+        import numpy as np
+        out = np.zeros((7, 2 * self.ny - 1, 2 * self.nx - 1))
+        nat.check(nat.load().gf_debug_kernel_table(self._h, int(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                  "gf_debug_kernel_table")
+        return out
+
+    def debug_spectrum(self, component, n):
+        import numpy as np
+        bit = components_mask([component]) if isinstance(component, str) else int(component)
+        out = np.zeros((self.info.px // 2 + 1, self.info.py // 2 + 1))
+        nat.check(nat.load().gf_debug_spectrum(self._h, ctypes.c_uint(bit), int(n),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                  "gf_debug_spectrum")
+        return out
+
+
+def plan(nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64", max_batch=0, device=None, stream=None):
+    return Plan(nx, ny, nz, dx, dy, dz, h, components, precision, max_batch, device, stream)
+
+
+def forward(p, rho, d=None, workspace=None, stream=None):
+    return p.forward(rho, d, workspace, stream)
+
+
+def adjoint(p, r, g=None, workspace=None, stream=None):
+    return p.adjoint(r, g, workspace, stream)
+
+
+class GravityForward(torch.autograd.Function):
+    """d = G rho with backward grad_rho = G^T grad_d (G is constant)."""
+
+    @staticmethod
+    def forward(ctx, rho, p):
+        ctx.plan = p
+        return p.forward(rho.contiguous())
+
+    @staticmethod
+    def backward(ctx, grad_d):
+        return ctx.plan.adjoint(grad_d.contiguous()), None
+
+
+class GravityOperator(torch.nn.Module):
+    """nn.Module wrapper: ``GravityOperator(plan)(rho) -> d``, differentiable in rho."""
+
+    def __init__(self, p):
+        super().__init__()
+        self.plan = p
+
+    def forward(self, rho):
+        return GravityForward.apply(rho, self.plan)

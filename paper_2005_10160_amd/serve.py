@@ -1,0 +1,510 @@
+"""Serving loop for the fast gravity operator: continuous batching over HIP
+streams with a geometry-keyed cache of resident kernel spectra.
+
+Requests carry a geometry (nx, ny, nz, dx, dy, dz, h, components), an
+operation (forward d = G rho or adjoint g = G^T r) and 1..B models.  The
+kernel spectra of a geometry are built once (the geometry/density split of
+section 2.2: the kernel does not change between calls) and stay resident
+while memory allows.
+
+``Scheduler`` is the policy, free of any device code so that it can run on a
+virtual clock in tests:
+  * pending requests are grouped by (geometry, operation); a launch takes
+    the group of the oldest pending request, in arrival order, up to
+    ``max_models`` models;
+  * a group is admitted when a stream slot is free and its bytes (workspace,
+    inputs and outputs, plus the spectra if they are not resident) fit in
+    the memory budget; idle cached spectra are evicted, least recently used
+    first, to make room;
+  * younger groups may pass an older one that does not fit yet, until the
+    older one has waited ``backfill_limit`` seconds: then admission stops
+    until memory drains for it;
+  * a request that can never fit is rejected at once; one that cannot be
+    admitted within ``admit_timeout`` is rejected; pending requests can be
+    cancelled.
+Requests that arrive while others run are admitted as soon as a slot and
+memory free up, and run concurrently on separate streams.
+
+``GpuExecutor`` launches groups through the HIP library, ``Server`` runs the
+scheduler in real time, and ``bench_served`` replays a seeded Poisson trace.
+"""
+
+import collections
+import heapq
+import itertools
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Any, Optional
+
+COMPONENT_COUNT = 7
+
+
+@dataclass(frozen=True)
+class GeometryKey:
+    nx: int
+    ny: int
+    nz: int
+    dx: float
+    dy: float
+    dz: float
+    h: float
+    components: int
+
+    @property
+    def n_out(self):
+        return bin(self.components & 0x7F).count("1")
+
+
+@dataclass
+class Request:
+    rid: int
+    key: GeometryKey
+    op: str                       # "forward" | "adjoint"
+    batch: int
+    t_arrival: float
+    data: Any = None              # [B][nz][ny][nx] (forward) or [B][C][ny][nx] (adjoint)
+    result: Any = None
+    status: str = "pending"       # pending | running | done | rejected | cancelled
+    error: Optional[str] = None
+    t_admit: Optional[float] = None
+    t_done: Optional[float] = None
+    event: threading.Event = field(default_factory=threading.Event, repr=False)
+
+    @property
+    def latency(self):
+        return None if self.t_done is None else self.t_done - self.t_arrival
+
+    def wait(self, timeout=None):
+        self.event.wait(timeout)
+        return self
+
+
+def _circulant(n):
+    p = 16
+    while p < 2 * n - 1:
+        p *= 2
+    return p
+
+
+def spectra_bytes(key: GeometryKey, elem: int) -> int:
+    """Resident spectra of a plan: one real per frequency of the quarter plane
+    for each stored component and layer."""
+    spec = key.components & 0x3F
+    if key.components & 0x40:
+        spec |= 0x12
+    n_spec = bin(spec).count("1")
+    return n_spec * key.nz * (_circulant(key.nx) // 2 + 1) * (_circulant(key.ny) // 2 + 1) * elem
+
+
+def io_bytes(key: GeometryKey, op: str, batch: int, elem: int) -> int:
+    plane = key.nx * key.ny
+    model = key.nz * plane
+    data = key.n_out * plane
+    return batch * (model + data) * elem
+
+
+class Scheduler:
+    """Admission and batching policy.  ``executor`` must provide
+    ``elem`` (bytes per value), ``workspace_bytes(key, op, batch)``,
+    ``is_resident(key)``, ``evict(key)``, ``launch(slot, requests)`` and
+    ``poll(slot) -> bool`` (True when the slot's launch has completed)."""
+
+    def __init__(self, executor, budget_bytes, n_slots=4, max_models=32, admit_timeout=30.0,
+                 backfill_limit=0.25, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.n_slots = int(n_slots)
+        self.max_models = int(max_models)
+        self.admit_timeout = admit_timeout
+        self.backfill_limit = backfill_limit
+        self.clock = clock
+        self.pending = collections.OrderedDict()      # (key, op) -> deque of requests
+        self.slots = [None] * self.n_slots            # slot -> (requests, bytes, key)
+        self.in_use = 0                               # bytes of running groups
+        self.resident = collections.OrderedDict()     # key -> bytes (LRU order)
+        self.busy_keys = collections.Counter()        # key -> running groups using it
+        self.completed = []
+        self.stats = collections.Counter()
+        self._seq = itertools.count()
+
+    # -- bookkeeping ---------------------------------------------------------
+    def resident_bytes(self):
+        return sum(self.resident.values())
+
+    def free_bytes(self):
+        return self.budget - self.in_use - self.resident_bytes()
+
+    def group_bytes(self, key, op, batch):
+        return self.ex.workspace_bytes(key, op, batch) + io_bytes(key, op, batch, self.ex.elem)
+
+    def submit(self, req: Request):
+        need = self.group_bytes(req.key, req.op, req.batch) + spectra_bytes(req.key, self.ex.elem)
+        if req.batch < 1 or req.batch > self.max_models or need > self.budget:
+            self._finish(req, "rejected", "request needs %d bytes / %d models; budget %d bytes / %d models"
+                         % (need, req.batch, self.budget, self.max_models))
+            return False
+        self.pending.setdefault((req.key, req.op), collections.deque()).append(req)
+        self.stats["submitted"] += 1
+        return True
+
+    def cancel(self, req: Request):
+        q = self.pending.get((req.key, req.op))
+        if q is not None and req in q and req.status == "pending":
+            q.remove(req)
+            if not q:
+                del self.pending[(req.key, req.op)]
+            self._finish(req, "cancelled", "cancelled by client")
+            return True
+        return False
+
+    def _finish(self, req, status, error=None):
+        req.status = status
+        req.error = error
+        req.t_done = self.clock()
+        self.stats[status] += 1
+        self.completed.append(req)
+        req.event.set()
+
+    # -- one scheduling step -------------------------------------------------
+    def step(self):
+        """Retire finished launches, expire waiters, admit what fits.
+        Returns the number of launches started."""
+        now = self.clock()
+        for s, entry in enumerate(self.slots):
+            if entry is not None and self.ex.poll(s):
+                reqs, nbytes, key = entry
+                self.slots[s] = None
+                self.in_use -= nbytes
+                self.busy_keys[key] -= 1
+                for r in reqs:
+                    if r.status == "running":
+                        self._finish(r, "done")
+        for k in list(self.pending):
+            q = self.pending[k]
+            while q and self.admit_timeout is not None and now - q[0].t_arrival > self.admit_timeout:
+                self._finish(q.popleft(), "rejected", "not admitted within %.3g s" % self.admit_timeout)
+            if not q:
+                del self.pending[k]
+        launched = 0
+        while self.pending and None in self.slots:
+            heads = sorted(self.pending.items(), key=lambda kv: kv[1][0].t_arrival)
+            oldest_wait = now - heads[0][1][0].t_arrival
+            chosen = None
+            for i, ((key, op), q) in enumerate(heads):
+                if i > 0 and oldest_wait > self.backfill_limit:
+                    break
+                group, models = [], 0
+                for r in q:
+                    if models + r.batch > self.max_models:
+                        break
+                    group.append(r)
+                    models += r.batch
+                nbytes = self.group_bytes(key, op, models)
+                miss = 0 if key in self.resident else spectra_bytes(key, self.ex.elem)
+                if self._make_room(nbytes + miss, key):
+                    chosen = (key, op, group, nbytes, miss)
+                    break
+            if chosen is None:
+                break
+            key, op, group, nbytes, miss = chosen
+            q = self.pending[(key, op)]
+            for r in group:
+                q.popleft()
+                r.status = "running"
+                r.t_admit = now
+            if not q:
+                del self.pending[(key, op)]
+            if miss:
+                self.resident[key] = miss
+                self.stats["spectra_miss"] += 1
+            else:
+                self.stats["spectra_hit"] += 1
+            self.resident.move_to_end(key)
+            slot = self.slots.index(None)
+            self.slots[slot] = (group, nbytes, key)
+            self.in_use += nbytes
+            self.busy_keys[key] += 1
+            self.stats["launches"] += 1
+            self.stats["batched_requests"] += len(group)
+            try:
+                self.ex.launch(slot, group)
+            except Exception as e:  # a failed launch fails its requests, not the loop
+                self.slots[slot] = None
+                self.in_use -= nbytes
+                self.busy_keys[key] -= 1
+                for r in group:
+                    self._finish(r, "rejected", "launch failed: %s" % e)
+                continue
+            launched += 1
+        return launched
+
+    def _make_room(self, need, key):
+        if need <= self.free_bytes():
+            return True
+        for k in list(self.resident):
+            if need <= self.free_bytes():
+                break
+            if k == key or self.busy_keys[k] > 0:
+                continue
+            del self.resident[k]
+            self.ex.evict(k)
+            self.stats["evictions"] += 1
+        return need <= self.free_bytes()
+
+    def idle(self):
+        return not self.pending and all(s is None for s in self.slots)
+
+
+# ---------------------------------------------------------------------------
+# GPU executor and real-time server
+# ---------------------------------------------------------------------------
+class GpuExecutor:
+    """Launches a group on one of ``n_slots`` HIP streams: host inputs are
+    copied into one batched device tensor, the operator runs once for the
+    whole group, and each request's slice is copied back to its host
+    buffer.  Plans (resident spectra) are built on a miss on their own
+    stream."""
+
+    def __init__(self, precision="f32", n_slots=4, device="cuda:0"):
+        import torch
+        from . import operator as op_mod
+        self.torch = torch
+        self.op_mod = op_mod
+        self.device = torch.device(device)
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "f32" else torch.float64
+        self.elem = 4 if precision == "f32" else 8
+        # all streams at the default priority
+        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_slots)]
+        self.plan_stream = torch.cuda.Stream(device=self.device)
+        self.plans = {}
+        self.events = [None] * n_slots
+        self.keep = [None] * n_slots
+        self.lock = threading.Lock()
+
+    def plan_for(self, key):
+        p = self.plans.get(key)
+        if p is None:
+            p = self.op_mod.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components,
+                                 self.precision, device=self.device, stream=self.plan_stream)
+            self.plans[key] = p
+        return p
+
+    def workspace_bytes(self, key, op, batch):
+        # the plan's own figure when it exists; otherwise an upper bound of the
+        # same layout (complex intermediates of the model and data sizes)
+        p = self.plans.get(key)
+        if p is not None:
+            return p.workspace_bytes(op, batch)
+        ux = _circulant(key.nx) // 2 + 1
+        nspec = 6
+        splits = 8
+        per = 2 * self.elem * ux * key.ny
+        return per * batch * (key.nz + splits * nspec)
+
+    def is_resident(self, key):
+        return key in self.plans
+
+    def evict(self, key):
+        p = self.plans.pop(key, None)
+        if p is not None:
+            self.plan_stream.synchronize()
+            p.close()
+
+    def launch(self, slot, reqs):
+        torch = self.torch
+        key, op = reqs[0].key, reqs[0].op
+        p = self.plan_for(key)
+        st = self.streams[slot]
+        B = sum(r.batch for r in reqs)
+        if op == "forward":
+            shape_in = (B, key.nz, key.ny, key.nx)
+            shape_out = (B, key.n_out, key.ny, key.nx)
+        else:
+            shape_in = (B, key.n_out, key.ny, key.nx)
+            shape_out = (B, key.nz, key.ny, key.nx)
+        with torch.cuda.stream(st):
+            x = torch.empty(shape_in, dtype=self.dtype, device=self.device)
+            y = torch.empty(shape_out, dtype=self.dtype, device=self.device)
+            ws = torch.empty(p.workspace_bytes(op, B), dtype=torch.uint8, device=self.device)
+            o = 0
+            for r in reqs:
+                x[o:o + r.batch].copy_(r.data, non_blocking=True)
+                o += r.batch
+            if op == "forward":
+                p.forward(x, y, ws, stream=st)
+            else:
+                p.adjoint(x, y, ws, stream=st)
+            o = 0
+            for r in reqs:
+                if r.result is None:
+                    r.result = torch.empty((r.batch,) + shape_out[1:], dtype=self.dtype, pin_memory=True)
+                r.result.copy_(y[o:o + r.batch], non_blocking=True)
+                o += r.batch
+            ev = torch.cuda.Event()
+            ev.record(st)
+        self.events[slot] = ev
+        self.keep[slot] = (x, y, ws)
+
+    def poll(self, slot):
+        ev = self.events[slot]
+        if ev is None or ev.query():
+            self.events[slot] = None
+            self.keep[slot] = None
+            return True
+        return False
+
+    def close(self):
+        self.torch.cuda.synchronize(self.device)
+        for p in self.plans.values():
+            p.close()
+        self.plans.clear()
+
+
+class Server:
+    """Real-time loop around a Scheduler: ``submit`` from any thread, a
+    background thread steps the scheduler."""
+
+    def __init__(self, executor, budget_bytes, n_slots=4, max_models=32, admit_timeout=30.0,
+                 backfill_limit=0.25):
+        self.sched = Scheduler(executor, budget_bytes, n_slots, max_models, admit_timeout, backfill_limit)
+        self.inbox = collections.deque()
+        self.cv = threading.Condition()
+        self.running = True
+        self.thread = threading.Thread(target=self._loop, daemon=True)
+        self.thread.start()
+
+    def submit(self, req: Request):
+        with self.cv:
+            self.inbox.append(req)
+            self.cv.notify()
+        return req
+
+    def cancel(self, req):
+        with self.cv:
+            self.inbox.append(("cancel", req))
+            self.cv.notify()
+
+    def _loop(self):
+        while True:
+            with self.cv:
+                while self.inbox:
+                    item = self.inbox.popleft()
+                    if isinstance(item, tuple):
+                        self.sched.cancel(item[1])
+                    else:
+                        self.sched.submit(item)
+                if not self.running and self.sched.idle():
+                    return
+            self.sched.step()
+            if self.sched.idle():
+                with self.cv:
+                    if not self.inbox and self.running:
+                        self.cv.wait(0.01)
+            else:
+                time.sleep(2e-5)
+
+    def close(self):
+        with self.cv:
+            self.running = False
+            self.cv.notify()
+        self.thread.join()
+
+
+def _percentiles(vals):
+    import numpy as np
+    if not vals:
+        return None, None
+    a = np.asarray(vals)
+    return float(np.percentile(a, 50)), float(np.percentile(a, 99))
+
+
+def make_inputs(trace, precision, device="cuda:0"):
+    """Pinned host inputs for a trace: one buffer per (shape, batch) is drawn
+    once (seeded) and shared by the requests that need it."""
+    import torch
+    dt = torch.float32 if precision == "f32" else torch.float64
+    pool = {}
+    gen = torch.Generator().manual_seed(500)
+    out = []
+    for tr in trace:
+        C = 6 if tr.full_tensor else 1
+        shape = (tr.batch, tr.nz, tr.n, tr.n) if tr.op == "forward" else (tr.batch, C, tr.n, tr.n)
+        k = (shape, tr.op)
+        if k not in pool:
+            t = torch.empty(shape, dtype=dt, pin_memory=True)
+            t.copy_(torch.rand(shape, generator=gen, dtype=torch.float64).sub_(0.5).mul_(1000.0))
+            pool[k] = t
+        out.append(pool[k])
+    return out
+
+
+def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=4, max_models=32,
+           time_limit=None):
+    """Replay arrivals in real time.  batched=False gives the plain baseline:
+    one stream, FIFO, one model per call."""
+    from synth.trace import TraceRequest  # noqa: F401  (trace records)
+    ex = executor_factory(n_slots if batched else 1)
+    if batched:
+        srv = Server(ex, budget_bytes, n_slots=n_slots, max_models=max_models, admit_timeout=None)
+    else:
+        srv = Server(ex, budget_bytes, n_slots=1, max_models=1, admit_timeout=None, backfill_limit=0.0)
+    reqs = []
+    t0 = time.perf_counter()
+    for tr, x in zip(trace, inputs):
+        if time_limit is not None and time.perf_counter() - t0 > time_limit:
+            break
+        key = GeometryKey(tr.n, tr.n, tr.nz, 20.0, 20.0, 20.0, 10.0, 0x3F if tr.full_tensor else 0x1)
+        delay = t0 + tr.t_arrival - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        if batched:
+            r = Request(tr.rid, key, tr.op, tr.batch, time.perf_counter(), x)
+            srv.submit(r)
+            reqs.append([r])
+        else:
+            # the plain operator: one model per call, in arrival order
+            t_arr = time.perf_counter()
+            parts = []
+            for b in range(tr.batch):
+                r = Request(tr.rid * 100 + b, key, tr.op, 1, t_arr, x[b:b + 1])
+                srv.submit(r)
+                parts.append(r)
+            reqs.append(parts)
+    for parts in reqs:
+        for r in parts:
+            r.wait()
+    wall = time.perf_counter() - t0
+    srv.close()
+    stats = dict(srv.sched.stats)
+    ex.close()
+    lat = []
+    evals = 0.0
+    for parts in reqs:
+        if all(r.status == "done" for r in parts):
+            lat.append(max(r.t_done for r in parts) - parts[0].t_arrival)
+            k = parts[0].key
+            evals += sum(r.batch for r in parts) * k.n_out * (k.nx * k.ny) ** 2 * k.nz
+    p50, p99 = _percentiles(lat)
+    return {"requests": len(reqs), "completed": len(lat), "wall_s": wall,
+            "p50_ms": None if p50 is None else p50 * 1e3, "p99_ms": None if p99 is None else p99 * 1e3,
+            "requests_per_s": len(lat) / wall, "effective_evals_per_s": evals / wall, "stats": stats}
+
+
+def bench_served(seconds=3.0, rate=200.0, budget_gb=64.0):
+    """Seeded Poisson trace (rate req/s) of mixed grids, replayed through the
+    FP32 continuous-batching server and through the plain FP64 operator
+    (FIFO, one model per call), both with the spectra cache on."""
+    from synth import poisson_trace
+    n = max(1, int(seconds * rate))
+    trace = poisson_trace(n_requests=n, rate=rate, seed=500)
+    budget = int(budget_gb * (1 << 30))
+    out = {"trace": "poisson %.0f req/s, %d requests (%.1f s), seed 500" % (rate, n, trace[-1].t_arrival)}
+    in32 = make_inputs(trace, "f32")
+    out["served_f32"] = replay(trace, in32, lambda k: GpuExecutor("f32", k), budget, batched=True)
+    del in32
+    in64 = make_inputs(trace, "f64")
+    out["plain_f64"] = replay(trace, in64, lambda k: GpuExecutor("f64", k), budget, batched=False,
+                              time_limit=4 * seconds)
+    return out
