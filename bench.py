@@ -56,13 +56,13 @@ def colpass_algorithmic_bytes(p, B):
     frequency; complex intermediates)."""
     info = p.info
     s = 8 if p.precision == "f64" else 4
-    U = info.px // 2 + 1
-    Q = info.py // 2 + 1
-    spectra = info.n_spec * info.nz * U * Q * s
-    R = B * info.nz * U * info.ny * 2 * s
+    M = info.px // 2            # column units (kx = 0 and Px/2 share unit 0)
+    Q = info.py // 2 + 1        # quarter-plane frequencies along y
+    spectra = info.n_spec * info.nz * (M + 1) * Q * s
+    R = B * info.nz * M * info.ny * 2 * s
     ws = p.workspace_bytes("forward", B)
-    S = round((ws // (2 * s * U * info.ny) - B * info.nz) / (B * info.n_spec))
-    D = S * B * info.n_spec * U * info.ny * 2 * s
+    S = round((ws // (2 * s * M * info.ny) - B * info.nz) / (B * info.n_spec))
+    D = S * B * info.n_spec * M * info.ny * 2 * s
     return spectra + R + D, S
 
 
@@ -134,6 +134,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=0.0)
     ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="also run a plain 1 GiB elementwise copy (read 1 GiB, write 1 GiB) so that "
+                         "hardware byte counters can be scaled")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -180,6 +183,15 @@ def main():
             res["adjoint_ms"] = (time.perf_counter() - t0) * 1e3 / steps
             res["adjoint_passes"] = time_passes(p, g_out, d, ws, steps, "adjoint")
         return res
+
+    if args.calibrate:
+        n = 1 << 28
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     evals = 6.0 * g.nd * g.nm
     main_res = run(args.precision, args.steps, args.warmup, not args.no_adjoint)

@@ -22,15 +22,79 @@ namespace gf {
 
 template <typename T, int N>
 struct ColCfg {
-    static constexpr int PPT = (sizeof(T) == 4) ? 8 : (N > 2048 ? 8 : 4);
+    static constexpr int PPT = 8;
     static constexpr int NT = N / PPT;
-    static constexpr int RADIX = PPT;
-    using FFT = BlockFFT<T, N, NT, RADIX>;
+    static constexpr int RADIX = 8;
+    // the transform of the hot passes: split re/im exchange, LDS twiddles
+    using FFT = BlockFFT<T, N, NT, RADIX, true, true>;
+    // the plan-time transform: full exchange, global twiddles
+    using FFTK = BlockFFT<T, N, NT, RADIX, false, false>;
     static constexpr int W = FFT::lds_words();
-    static constexpr int THREADS = NT >= 256 ? NT : 256;
-    static constexpr int G = THREADS / NT;          // groups (column units) per workgroup
-    static constexpr size_t LDS = (size_t)G * 2 * W * sizeof(T);
+    static constexpr int VEC = 16 / (int)sizeof(T);                  // values per 16 bytes
+    static constexpr int up(int x) { return ((x + VEC - 1) / VEC) * VEC; }
+    static constexpr int XW = up(W);                                  // exchange words
+    static constexpr int TWW = up(2 * (N / 4 + 1));                   // quarter twiddle table words
+    static constexpr int QP = up(N / 2 + 1);                          // padded spectrum row
+    static constexpr int CB = up(2 * (N / 2));                        // one column buffer (ldc <= N/2)
+    // T words per group: exchange, twiddles, two column buffers (forward) and
+    // two spectrum buffers of cmax rows
+    static constexpr int group_words(int cmax, bool fwd) { return XW + TWW + (fwd ? 2 * CB : 0) + 2 * cmax * QP; }
+    // groups (column units) per workgroup: up to 256 threads for short
+    // transforms, as long as the largest variant stays within 64 KB of LDS
+    static constexpr int groups()
+    {
+        int g = NT >= 256 ? 1 : 256 / NT;
+        while (g > 1 && (size_t)g * group_words(6, true) * sizeof(T) > 64 * 1024) g /= 2;
+        return g;
+    }
+    static constexpr int G = groups();
+    static constexpr int THREADS = G * NT;
+    static constexpr bool ASYNC = (NT % 64) == 0;                     // groups are whole waves
+    static constexpr size_t lds_bytes(int cmax, bool fwd) { return (size_t)G * group_words(cmax, fwd) * sizeof(T); }
+    // register target: FP32 workgroups fit two per CU by LDS, so ask for two
+    // waves per SIMD (at most 256 registers a lane); FP64 ones fit one.
+    static constexpr int WAVES_PER_EU = sizeof(T) == 4 ? (THREADS <= 256 ? 2 : 1) : 1;
 };
+
+// Row of the resident spectra holding x-bin kx: rows are stored in the order
+// kx = 0, Px/2, 1, 2, ..., Px/2-1 so that the two real-valued bins that share
+// packed unit 0 are adjacent.
+__device__ __forceinline__ unsigned spec_row(unsigned kx, unsigned M)
+{
+    return kx == 0 ? 0u : (kx == M ? 1u : kx + 1u);
+}
+
+// Copy `nvals` contiguous values (a multiple of 16 bytes) from global memory
+// into this group's LDS buffer.  Whole-wave groups use the asynchronous
+// global-to-LDS path (no registers; completion is awaited with a vmcnt wait);
+// otherwise plain loads and stores.
+template <typename T, int NT, bool ASYNC>
+__device__ __forceinline__ void stage_rows(const T *__restrict__ src, T *dst, unsigned nvals, unsigned t)
+{
+    if constexpr (ASYNC) {
+        constexpr unsigned VEC = 16 / sizeof(T);
+        const unsigned nvec = nvals / VEC;
+        const unsigned wave_off = __builtin_amdgcn_readfirstlane((t / 64) * 64);
+        for (unsigned i = 0; i < nvec; i += NT) {
+            if (i + t < nvec) {
+                // lane l of the wave lands at LDS base + 16 l
+                auto *lds = (__attribute__((address_space(3))) void *)(dst + (size_t)(i + wave_off) * VEC);
+                __builtin_amdgcn_global_load_lds((const void *)(src + (size_t)(i + t) * VEC), lds, 16, 0, 0);
+            }
+        }
+    } else {
+        for (unsigned i = t; i < nvals; i += NT) dst[i] = src[i];
+    }
+}
+
+// All of this wave's staged copies have landed, and every wave is past its
+// reads of the buffers about to be refilled.
+template <bool ASYNC>
+__device__ __forceinline__ void stage_wait()
+{
+    if constexpr (ASYNC) __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+}
 
 // reorder registers from the FFT output layout to the FFT input layout
 // (both are strided by NT; only the slot order differs)
@@ -48,31 +112,103 @@ __device__ __forceinline__ void out_to_in(cx<T> (&v)[PPT])
     }
 }
 
+// Column of unit u in a slab laid out [unit][y].  Units are the Px/2 x-bins
+// kx = 1 .. Px/2-1 plus unit 0, which packs the two real-valued bins kx = 0
+// (real part) and kx = Px/2 (imaginary part).
+template <typename T>
+__device__ __forceinline__ const cx<T> *column(const cx<T> *base, size_t slab, unsigned M, unsigned u,
+                                               unsigned ny)
+{
+    return base + (slab * M + u) * (size_t)ny;
+}
+
+// Work of one group: virtual unit uv in [0, M] of model b.  uv = 0 and
+// uv = M are the kx = 0 and kx = Px/2 bins, read from the real and the
+// imaginary part of packed unit 0 and written back into them.
+struct Unit {
+    unsigned uv, u, b;
+    int part;  // 0: whole complex column, 1: real part, 2: imaginary part
+    bool active;
+};
+
+template <int NT, int G>
+__device__ __forceinline__ Unit unit_of(unsigned g, int M, int B)
+{
+    Unit w;
+    const unsigned U1 = (unsigned)M + 1;
+    const unsigned gi = blockIdx.x * G + g;
+    w.active = gi < U1 * (unsigned)B;
+    w.uv = w.active ? gi / B : (unsigned)M;
+    w.b = w.active ? gi % B : 0;
+    if (NT >= 64) {  // a group is whole waves: keep its indices in scalar registers
+        w.uv = __builtin_amdgcn_readfirstlane(w.uv);
+        w.b = __builtin_amdgcn_readfirstlane(w.b);
+    }
+    w.u = (w.uv == (unsigned)M) ? 0u : w.uv;
+    w.part = w.uv == 0 ? 1 : (w.uv == (unsigned)M ? 2 : 0);
+    return w;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> take_part(cx<T> x, int part)
+{
+    if (part == 1) x.im = T(0);
+    if (part == 2) x = cx<T>{x.im, T(0)};
+    return x;
+}
+
+template <typename T, int PPT, typename F, int NT>
+__device__ __forceinline__ void store_column(cx<T> *dst, const cx<T> (&v)[PPT], unsigned t, int ny, int part)
+{
+    T *dsc = reinterpret_cast<T *>(dst);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const unsigned y = t + NT * F::elem_out(s);
+        if (y < (unsigned)ny) {
+            if (part == 0)
+                dst[y] = v[s];
+            else
+                dsc[2 * y + (part - 1)] = v[s].re;
+        }
+    }
+}
+
+// Forward column pass.  Per layer n of the split: the density column and the
+// spectrum rows of layer n+1 stream into LDS (asynchronously) while layer n's
+// column is transformed along y and each component accumulates
+// conj(K^_{c,n}) times it; after the last layer one inverse transform per
+// component.  All global reads of the loop are asynchronous copies into LDS.
 template <typename T, int N, int CMAX>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(ColCfg<T, N>::WAVES_PER_EU)))
     col_forward_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec,
-                       cx<T> *__restrict__ D, int B, int nz, int U, int ny, int Cs, int lps,
+                       cx<T> *__restrict__ D, int B, int nz, int M, int ny, int ldc, int Cs, int lps,
                        unsigned imag_mask, unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
 {
     using C = ColCfg<T, N>;
     using F = typename C::FFT;
-    constexpr int PPT = C::PPT, NT = C::NT, G = C::G, W = C::W;
-    constexpr int Q = N / 2 + 1;
+    constexpr int PPT = C::PPT, NT = C::NT, G = C::G, QP = C::QP;
+    constexpr int CB = C::CB;
+    constexpr bool AS = C::ASYNC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
 
-    const int g = threadIdx.x / NT;
-    const int t = threadIdx.x % NT;
-    T *sre = lds + (size_t)g * 2 * W;
-    T *sim = sre + W;
+    const unsigned g = threadIdx.x / NT;
+    const unsigned t = threadIdx.x % NT;
+    T *xbuf = lds + (size_t)g * C::group_words(CMAX, true);
+    T *twq = xbuf + C::XW;
+    T *cbuf = twq + C::TWW;                  // two column buffers
+    T *sbuf = cbuf + 2 * CB;                 // two spectrum buffers
+    load_quarter<T, N>(twq, twq + (N / 4 + 1), tw, twlog, t, NT);
 
-    const long gi = (long)blockIdx.x * G + g;
-    const bool active = gi < (long)U * B;
-    const int u = active ? (int)(gi / B) : 0;
-    const int b = active ? (int)(gi % B) : 0;
+    const Unit w = unit_of<NT, G>(g, M, B);
+    const unsigned row = spec_row(w.uv, (unsigned)M);
+    const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
+    const unsigned col_vals = 2u * (unsigned)ldc;   // ldc keeps every column 16-byte aligned
     const int split = blockIdx.y;
     const int n0 = split * lps;
     const int n1 = min(nz, n0 + lps);
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
 
     cx<T> acc[CMAX][PPT];
 #pragma unroll
@@ -80,28 +216,43 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
         for (int s = 0; s < PPT; ++s) acc[c][s] = cx<T>{T(0), T(0)};
 
+    if (n0 < n1) {
+        stage_rows<T, NT, AS>(reinterpret_cast<const T *>(column(R, (size_t)w.b * nz + n0, M, w.u, ldc)), cbuf,
+                              col_vals, t);
+        stage_rows<T, NT, AS>(spec + (size_t)n0 * layer_vals + (size_t)row * Cs * QP, sbuf, (unsigned)Cs * QP, t);
+    }
+    stage_wait<AS>();
+
     for (int n = n0; n < n1; ++n) {
+        const int cur = (n - n0) & 1;
+        const T *ccur = cbuf + cur * CB;
+        const T *scur = sbuf + cur * CMAX * QP;
+        if (n + 1 < n1) {
+            stage_rows<T, NT, AS>(reinterpret_cast<const T *>(column(R, (size_t)w.b * nz + n + 1, M, w.u, ldc)),
+                                  cbuf + (cur ^ 1) * CB, col_vals, t);
+            stage_rows<T, NT, AS>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
+                                  sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, t);
+        }
         cx<T> v[PPT];
-        const cx<T> *col = R + (((long)b * nz + n) * U + u) * (long)ny;
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
-            const int y = t + NT * F::elem_in(s);
-            v[s] = (active && y < ny) ? col[y] : cx<T>{T(0), T(0)};
+            const unsigned y = t + NT * F::elem_in(s);
+            v[s] = cx<T>{T(0), T(0)};
+            if (y < (unsigned)ny) v[s] = take_part(cx<T>{ccur[2 * y], ccur[2 * y + 1]}, w.part);
         }
-        F::template run<false>(v, sre, sim, t, tw, twlog);
+        F::template run<false>(v, xbuf, nullptr, t, twp, twlog);
 #pragma unroll
         for (int c = 0; c < CMAX; ++c) {
             if (c < Cs) {
-                const T *sp = spec + ((long)(c * nz + n) * U + u) * (long)Q;
                 const bool im = (imag_mask >> c) & 1u;
                 const bool yo = (yodd_mask >> c) & 1u;
 #pragma unroll
                 for (int s = 0; s < PPT; ++s) {
-                    const int ky = t + NT * F::elem_out(s);
-                    const int kq = ky <= N / 2 ? ky : N - ky;
-                    T k = active ? sp[kq] : T(0);
+                    const unsigned ky = t + NT * F::elem_out(s);
+                    const unsigned kq = ky <= N / 2 ? ky : N - ky;
+                    T k = scur[c * QP + kq];
                     if (yo && ky > N / 2) k = -k;
-                    if (im) {  // conj(i k) v = -i k v
+                    if (im) {  // the kernel spectrum is i k and enters conjugated: -i k v
                         acc[c][s].re += k * v[s].im;
                         acc[c][s].im -= k * v[s].re;
                     } else {
@@ -111,47 +262,49 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
                 }
             }
         }
+        stage_wait<AS>();
     }
 
 #pragma unroll
     for (int c = 0; c < CMAX; ++c) {
         if (c < Cs) {
             out_to_in<F, T, PPT>(acc[c]);
-            F::template run<true>(acc[c], sre, sim, t, tw, twlog);
-            if (active) {
-                cx<T> *dst = D + ((((long)split * B + b) * Cs + c) * U + u) * (long)ny;
-#pragma unroll
-                for (int s = 0; s < PPT; ++s) {
-                    const int y = t + NT * F::elem_out(s);
-                    if (y < ny) dst[y] = acc[c][s];
-                }
-            }
+            F::template run<true>(acc[c], xbuf, nullptr, t, twp, twlog);
+            if (w.active)
+                store_column<T, PPT, F, NT>(D + ((((size_t)split * B + w.b) * Cs + c) * M + w.u) * (size_t)ldc,
+                                            acc[c], t, ny, w.part);
         }
     }
 }
 
+// Adjoint column pass: the Cs residual columns are transformed once; per
+// layer the spectrum rows of the next layer stream into LDS while
+// sum_c K^_{c,n} r^_c is formed and inverse-transformed.
 template <typename T, int N, int CMAX>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(ColCfg<T, N>::WAVES_PER_EU)))
     col_adjoint_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec,
-                       cx<T> *__restrict__ Gout, int B, int nz, int U, int ny, int Cs, int lps,
+                       cx<T> *__restrict__ Gout, int B, int nz, int M, int ny, int ldc, int Cs, int lps,
                        unsigned imag_mask, unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
 {
     using C = ColCfg<T, N>;
     using F = typename C::FFT;
-    constexpr int PPT = C::PPT, NT = C::NT, G = C::G, W = C::W;
-    constexpr int Q = N / 2 + 1;
+    constexpr int PPT = C::PPT, NT = C::NT, G = C::G, QP = C::QP;
+    constexpr bool AS = C::ASYNC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
 
-    const int g = threadIdx.x / NT;
-    const int t = threadIdx.x % NT;
-    T *sre = lds + (size_t)g * 2 * W;
-    T *sim = sre + W;
+    const unsigned g = threadIdx.x / NT;
+    const unsigned t = threadIdx.x % NT;
+    T *xbuf = lds + (size_t)g * C::group_words(CMAX, false);
+    T *twq = xbuf + C::XW;
+    T *sbuf = twq + C::TWW;
+    load_quarter<T, N>(twq, twq + (N / 4 + 1), tw, twlog, t, NT);
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
 
-    const long gi = (long)blockIdx.x * G + g;
-    const bool active = gi < (long)U * B;
-    const int u = active ? (int)(gi / B) : 0;
-    const int b = active ? (int)(gi % B) : 0;
+    const Unit w = unit_of<NT, G>(g, M, B);
+    const unsigned row = spec_row(w.uv, (unsigned)M);
+    const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
     const int split = blockIdx.y;
     const int n0 = split * lps;
     const int n1 = min(nz, n0 + lps);
@@ -159,35 +312,45 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     cx<T> rh[CMAX][PPT];
 #pragma unroll
     for (int c = 0; c < CMAX; ++c) {
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) rh[c][s] = cx<T>{T(0), T(0)};
         if (c < Cs) {
-            const cx<T> *col = R + (((long)b * Cs + c) * U + u) * (long)ny;
+            const cx<T> *col = column(R, (size_t)w.b * Cs + c, M, w.u, ldc);
 #pragma unroll
             for (int s = 0; s < PPT; ++s) {
-                const int y = t + NT * F::elem_in(s);
-                rh[c][s] = (active && y < ny) ? col[y] : cx<T>{T(0), T(0)};
+                const unsigned y = t + NT * F::elem_in(s);
+                if (y < (unsigned)ny) rh[c][s] = take_part(col[y], w.part);
             }
-            F::template run<false>(rh[c], sre, sim, t, tw, twlog);
-        } else {
-#pragma unroll
-            for (int s = 0; s < PPT; ++s) rh[c][s] = cx<T>{T(0), T(0)};
         }
     }
+    __syncthreads();   // twiddle table complete
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+        if (c < Cs) F::template run<false>(rh[c], xbuf, nullptr, t, twp, twlog);
+
+    if (n0 < n1)
+        stage_rows<T, NT, AS>(spec + (size_t)n0 * layer_vals + (size_t)row * Cs * QP, sbuf, (unsigned)Cs * QP, t);
+    stage_wait<AS>();
 
     for (int n = n0; n < n1; ++n) {
+        const int cur = (n - n0) & 1;
+        const T *scur = sbuf + cur * CMAX * QP;
+        if (n + 1 < n1)
+            stage_rows<T, NT, AS>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
+                                  sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, t);
         cx<T> v[PPT];
 #pragma unroll
         for (int s = 0; s < PPT; ++s) v[s] = cx<T>{T(0), T(0)};
 #pragma unroll
         for (int c = 0; c < CMAX; ++c) {
             if (c < Cs) {
-                const T *sp = spec + ((long)(c * nz + n) * U + u) * (long)Q;
                 const bool im = (imag_mask >> c) & 1u;
                 const bool yo = (yodd_mask >> c) & 1u;
 #pragma unroll
                 for (int s = 0; s < PPT; ++s) {
-                    const int ky = t + NT * F::elem_out(s);
-                    const int kq = ky <= N / 2 ? ky : N - ky;
-                    T k = active ? sp[kq] : T(0);
+                    const unsigned ky = t + NT * F::elem_out(s);
+                    const unsigned kq = ky <= N / 2 ? ky : N - ky;
+                    T k = scur[c * QP + kq];
                     if (yo && ky > N / 2) k = -k;
                     if (im) {  // (i k) r
                         v[s].re -= k * rh[c][s].im;
@@ -200,104 +363,111 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
             }
         }
         out_to_in<F, T, PPT>(v);
-        F::template run<true>(v, sre, sim, t, tw, twlog);
-        if (active) {
-            cx<T> *dst = Gout + (((long)b * nz + n) * U + u) * (long)ny;
-#pragma unroll
-            for (int s = 0; s < PPT; ++s) {
-                const int y = t + NT * F::elem_out(s);
-                if (y < ny) dst[y] = v[s];
-            }
-        }
+        F::template run<true>(v, xbuf, nullptr, t, twp, twlog);
+        if (w.active)
+            store_column<T, PPT, F, NT>(Gout + (((size_t)w.b * nz + n) * M + w.u) * (size_t)ldc, v, t, ny, w.part);
+        stage_wait<AS>();
     }
 }
 
 // Plan time: full-length column FFT of the row-transformed kernel fields
-// (double), keeping one real per frequency of the quarter plane.
+// (double), keeping one real per frequency of the quarter plane.  Virtual
+// units as in the adjoint.
 template <typename TO, int N>
 __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
     col_kgen_kernel(const cx<double> *__restrict__ Rk, TO *__restrict__ spec, int nl, int n0, int Cs,
-                    int nz, int U, unsigned imag_mask, const cx<double> *__restrict__ tw, int twlog)
+                    int nz, int M, unsigned imag_mask, const cx<double> *__restrict__ tw, int twlog)
 {
     using C = ColCfg<double, N>;
-    using F = typename C::FFT;
-    constexpr int PPT = C::PPT, NT = C::NT, G = C::G, W = C::W;
-    constexpr int Q = N / 2 + 1;
+    using F = typename C::FFTK;
+    constexpr int PPT = C::PPT, NT = C::NT, G = C::G, W = F::lds_words();
+    constexpr unsigned QPO = ColCfg<TO, N>::QP;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     double *lds = reinterpret_cast<double *>(smem_raw);
-    const int g = threadIdx.x / NT;
-    const int t = threadIdx.x % NT;
+    const unsigned g = threadIdx.x / NT;
+    const unsigned t = threadIdx.x % NT;
     double *sre = lds + (size_t)g * 2 * W;
     double *sim = sre + W;
 
-    const long npair = (long)nl * Cs;
-    const long gi = (long)blockIdx.x * G + g;
-    const bool active = gi < npair * U;
-    const long pair = active ? gi / U : 0;
-    const int u = active ? (int)(gi % U) : 0;
+    const unsigned U1 = M + 1;
+    const unsigned npair = (unsigned)(nl * Cs);
+    const unsigned gi = blockIdx.x * G + g;
+    const bool active = gi < npair * U1;
+    const unsigned pair = active ? gi / U1 : 0;
+    const unsigned uv = active ? gi % U1 : 0;
+    const unsigned u = (uv == (unsigned)M) ? 0u : uv;
+    const int part = uv == 0 ? 1 : (uv == (unsigned)M ? 2 : 0);
     const int c = (int)(pair % Cs);
     const int n = n0 + (int)(pair / Cs);
 
     cx<double> v[PPT];
-    const cx<double> *col = Rk + (pair * U + u) * (long)N;
+    const cx<double> *col = column(Rk, pair, M, u, N);
 #pragma unroll
     for (int s = 0; s < PPT; ++s) {
-        const int y = t + NT * F::elem_in(s);
-        v[s] = active ? col[y] : cx<double>{0.0, 0.0};
+        const unsigned y = t + NT * F::elem_in(s);
+        cx<double> x = active ? col[y] : cx<double>{0.0, 0.0};
+        if (part == 1) x.im = 0.0;
+        if (part == 2) x = cx<double>{x.im, 0.0};
+        v[s] = x;
     }
     F::template run<false>(v, sre, sim, t, tw, twlog);
     if (active) {
         const bool im = (imag_mask >> c) & 1u;
-        TO *dst = spec + ((long)(c * nz + n) * U + u) * (long)Q;
+        TO *dst = spec + (((size_t)n * U1 + spec_row(uv, M)) * Cs + c) * QPO;
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
-            const int ky = t + NT * F::elem_out(s);
+            const unsigned ky = t + NT * F::elem_out(s);
             if (ky <= N / 2) dst[ky] = (TO)(im ? v[s].im : v[s].re);
         }
+        // zero the row padding so staged blocks hold no stale values
+        if (t < QPO - (N / 2 + 1)) dst[N / 2 + 1 + t] = TO(0);
     }
 }
 
 template <typename T, int N, int CMAX>
-static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int U, int ny, int Cs,
+static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc, int Cs,
                    int nsplit, int lps, unsigned imag_mask, unsigned yodd_mask, const void *tw,
                    int twlog, hipStream_t st)
 {
     using C = ColCfg<T, N>;
-    const long groups = (long)U * B;
+    const long groups = (long)(M + 1) * B;
     const long nblk = (groups + C::G - 1) / C::G;
-    if (C::LDS > lds_limit()) return -3;
+    const size_t lds = C::lds_bytes(CMAX, true);
+    if (lds > lds_limit()) return -3;
     hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX>), dim3((unsigned)nblk, (unsigned)nsplit),
-                       dim3(C::THREADS), C::LDS, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
-                       B, nz, U, ny, Cs, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+                       dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
+                       B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T, int N, int CMAX>
-static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, int U, int ny, int Cs,
+static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc, int Cs,
                    int nsplit, int lps, unsigned imag_mask, unsigned yodd_mask, const void *tw,
                    int twlog, hipStream_t st)
 {
     using C = ColCfg<T, N>;
-    const long groups = (long)U * B;
+    const long groups = (long)(M + 1) * B;
     const long nblk = (groups + C::G - 1) / C::G;
-    if (C::LDS > lds_limit()) return -3;
+    const size_t lds = C::lds_bytes(CMAX, false);
+    if (lds > lds_limit()) return -3;
     hipLaunchKernelGGL((col_adjoint_kernel<T, N, CMAX>), dim3((unsigned)nblk, (unsigned)nsplit),
-                       dim3(C::THREADS), C::LDS, st, (const cx<T> *)R, (const T *)spec,
-                       (cx<T> *)Gout, B, nz, U, ny, Cs, lps, imag_mask, yodd_mask,
+                       dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec,
+                       (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask,
                        (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename TO, int N>
-static int run_kgen(const void *Rk, void *spec, int nl, int n0, int Cs, int nz, int U,
+static int run_kgen(const void *Rk, void *spec, int nl, int n0, int Cs, int nz, int M,
                     unsigned imag_mask, const void *tw, int twlog, hipStream_t st)
 {
     using C = ColCfg<double, N>;
-    const long groups = (long)nl * Cs * U;
+    const long groups = (long)nl * Cs * (M + 1);
     const long nblk = (groups + C::G - 1) / C::G;
-    if (C::LDS > lds_limit()) return -3;
-    hipLaunchKernelGGL((col_kgen_kernel<TO, N>), dim3((unsigned)nblk), dim3(C::THREADS), C::LDS, st,
-                       (const cx<double> *)Rk, (TO *)spec, nl, n0, Cs, nz, U, imag_mask,
+    const size_t lds = (size_t)C::G * 2 * C::FFTK::lds_words() * sizeof(double);
+    if (lds > lds_limit()) return -3;
+    hipLaunchKernelGGL((col_kgen_kernel<TO, N>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
+                       (const cx<double> *)Rk, (TO *)spec, nl, n0, Cs, nz, M, imag_mask,
                        (const cx<double> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
@@ -305,35 +475,35 @@ static int run_kgen(const void *Rk, void *spec, int nl, int n0, int Cs, int nz, 
 #define GF_COL_SIZES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
 template <typename T, int N>
-static int fwd_c(int Cs, const void *R, const void *spec, void *D, int B, int nz, int U, int ny,
+static int fwd_c(int Cs, const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc,
                  int nsplit, int lps, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
-    if (Cs <= 1) return run_fwd<T, N, 1>(R, spec, D, B, nz, U, ny, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_fwd<T, N, 3>(R, spec, D, B, nz, U, ny, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    return run_fwd<T, N, 6>(R, spec, D, B, nz, U, ny, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_fwd<T, N, 1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_fwd<T, N, 3>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    return run_fwd<T, N, 6>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
 }
 
 template <typename T, int N>
-static int adj_c(int Cs, const void *R, const void *spec, void *Gout, int B, int nz, int U, int ny,
+static int adj_c(int Cs, const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc,
                  int nsplit, int lps, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
-    if (Cs <= 1) return run_adj<T, N, 1>(R, spec, Gout, B, nz, U, ny, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_adj<T, N, 3>(R, spec, Gout, B, nz, U, ny, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    return run_adj<T, N, 6>(R, spec, Gout, B, nz, U, ny, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_adj<T, N, 1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_adj<T, N, 3>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    return run_adj<T, N, 6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
 }
 
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
-                       int U, int ny, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
     if (Cs < 1 || Cs > 6) return -2;
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
-        return fp64 ? fwd_c<double, NN>(Cs, R, spec, D, B, nz, U, ny, nsplit, lps, imag_mask,    \
+        return fp64 ? fwd_c<double, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, imag_mask,    \
                                         yodd_mask, tw, twlog, st)                                \
-                    : fwd_c<float, NN>(Cs, R, spec, D, B, nz, U, ny, nsplit, lps, imag_mask,     \
+                    : fwd_c<float, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, imag_mask,     \
                                        yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
@@ -344,15 +514,15 @@ int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void 
 }
 
 int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
-                       int nz, int U, int ny, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
     if (Cs < 1 || Cs > 6) return -2;
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
-        return fp64 ? adj_c<double, NN>(Cs, R, spec, Gout, B, nz, U, ny, nsplit, lps, imag_mask, \
+        return fp64 ? adj_c<double, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, imag_mask, \
                                         yodd_mask, tw, twlog, st)                                \
-                    : adj_c<float, NN>(Cs, R, spec, Gout, B, nz, U, ny, nsplit, lps, imag_mask,  \
+                    : adj_c<float, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, imag_mask,  \
                                        yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
@@ -363,12 +533,12 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
 }
 
 int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,
-                    int nz, int U, unsigned imag_mask, const void *tw, int twlog, hipStream_t st)
+                    int nz, int M, unsigned imag_mask, const void *tw, int twlog, hipStream_t st)
 {
 #define CASE(NN)                                                                                  \
     case NN:                                                                                      \
-        return out_fp64 ? run_kgen<double, NN>(Rk, spec, nl, n0, Cs, nz, U, imag_mask, tw, twlog, st) \
-                        : run_kgen<float, NN>(Rk, spec, nl, n0, Cs, nz, U, imag_mask, tw, twlog, st);
+        return out_fp64 ? run_kgen<double, NN>(Rk, spec, nl, n0, Cs, nz, M, imag_mask, tw, twlog, st) \
+                        : run_kgen<float, NN>(Rk, spec, nl, n0, Cs, nz, M, imag_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
     default:
@@ -384,11 +554,14 @@ static int capacity_of(int Cs)
     hipError_t e;
     using C = ColCfg<T, N>;
     if (Cs <= 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 1>, C::THREADS, C::LDS);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 1>, C::THREADS,
+                                                         C::lds_bytes(1, true));
     else if (Cs <= 3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 3>, C::THREADS, C::LDS);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 3>, C::THREADS,
+                                                         C::lds_bytes(3, true));
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 6>, C::THREADS, C::LDS);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 6>, C::THREADS,
+                                                         C::lds_bytes(6, true));
     if (e != hipSuccess || nb < 1) nb = 1;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -424,6 +597,40 @@ size_t lds_limit()
         cached_dev = dev;
     }
     return cached;
+}
+
+int spec_row_pitch(bool fp64, int py)
+{
+#define CASE(NN) \
+    case NN:     \
+        return fp64 ? ColCfg<double, NN>::QP : ColCfg<float, NN>::QP;
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return 0;
+    }
+#undef CASE
+}
+
+template <typename T, int N>
+static bool supported_of(int Cs)
+{
+    using C = ColCfg<T, N>;
+    const int cmax = Cs <= 1 ? 1 : (Cs <= 3 ? 3 : 6);
+    return C::lds_bytes(cmax, true) <= lds_limit() && C::lds_bytes(cmax, false) <= lds_limit();
+}
+
+bool col_supported(bool fp64, int py, int Cs)
+{
+#define CASE(NN) \
+    case NN:     \
+        return fp64 ? supported_of<double, NN>(Cs) : supported_of<float, NN>(Cs);
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return false;
+    }
+#undef CASE
 }
 
 int col_forward_groups(bool fp64, int py)

@@ -110,10 +110,55 @@ struct dft<T, 8, INV> {
 // ------------------------------------------------------------ twiddles ----
 // tw[m] = exp(-2 pi i m / TL) for m in [0, TL), TL = 2^twlog (a power of two
 // no smaller than any transform length in use).  W(a, L) = exp(-+2 pi i a / L).
-template <typename T, bool INV>
-__device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog, int a, int logL)
+//
+// The table pointer is passed through an empty asm statement at every stage:
+// the compiler then cannot hoist twiddle loads out of the stage (or out of a
+// loop that repeats the transform), which would keep dozens of values live
+// in registers for the whole kernel.
+template <typename T>
+__device__ __forceinline__ const cx<T> *opaque(const cx<T> *p)
 {
-    cx<T> w = tw[a << (twlog - logL)];
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Twiddles of a length-N transform from a quarter-wave table in LDS,
+// q[r] = exp(-2 pi i r / N) for r in [0, N/4]:  exp(-2 pi i m / N) =
+// q[m mod N/4] * (-i)^(m div N/4).
+template <typename T, int N, bool INV>
+__device__ __forceinline__ cx<T> twiddle_q(const T *qre, const T *qim, unsigned a, int logL)
+{
+    constexpr int LOGN = ilog2<N>::value;
+    const unsigned m = (a << (unsigned)(LOGN - logL)) & (N - 1);
+    const unsigned r = m & (N / 4 - 1);
+    const unsigned q = m >> (LOGN - 2);
+    const T c = qre[r], s = qim[r];
+    cx<T> w;
+    switch (q) {
+    case 0: w = cx<T>{c, s}; break;
+    case 1: w = cx<T>{s, -c}; break;      // times -i
+    case 2: w = cx<T>{-c, -s}; break;     // times -1
+    default: w = cx<T>{-s, c}; break;     // times +i
+    }
+    return INV ? conjg(w) : w;
+}
+
+// Fill the quarter table of length N from the global table (length 2^twlog).
+template <typename T, int N>
+__device__ __forceinline__ void load_quarter(T *qre, T *qim, const cx<T> *__restrict__ tw, int twlog,
+                                             unsigned tid, unsigned nthreads)
+{
+    constexpr int LOGN = ilog2<N>::value;
+    for (unsigned r = tid; r <= N / 4; r += nthreads) {
+        const cx<T> w = tw[r << (unsigned)(twlog - LOGN)];
+        qre[r] = w.re;
+        qim[r] = w.im;
+    }
+}
+template <typename T, bool INV>
+__device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog, unsigned a, int logL)
+{
+    cx<T> w = tw[a << (unsigned)(twlog - logL)];
     return INV ? conjg(w) : w;
 }
 
@@ -125,9 +170,13 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog
 // Register slot v[m R + k] of thread t holds element t + NT (m + k PPT/R);
 // with R = PPT this is element t + NT k.  The same layout holds on output
 // (with the radix of the last stage), so callers index slots through
-// elem_in()/elem_out().  LDS: two arrays (re, im) of lds_words() entries per
-// group, padded by one word every R to spread banks.
-template <typename T, int N, int NT, int R>
+// elem_in()/elem_out().
+//
+// LDS per group: with XSPLIT = false, two arrays (re, im) of lds_words()
+// entries; with XSPLIT = true one array, through which the real and the
+// imaginary parts are exchanged one after the other (half the LDS, twice the
+// barriers).  Indices are padded by one word every R to spread banks.
+template <typename T, int N, int NT, int R, bool XSPLIT = false, bool TWQ = false>
 struct BlockFFT {
     static constexpr int PPT = N / NT;
     static constexpr int LOGN = ilog2<N>::value;
@@ -138,7 +187,9 @@ struct BlockFFT {
     static constexpr int NSTAGES = (LOGN + LOGR - 1) / LOGR;
 
     __host__ __device__ static constexpr int lds_words() { return N + N / R + 1; }
-    __device__ __forceinline__ static int pad(int i) { return i + (i >> LOGR); }
+    // T words of LDS one group needs
+    __host__ __device__ static constexpr int lds_group_words() { return (XSPLIT ? 1 : 2) * lds_words(); }
+    __device__ __forceinline__ static unsigned pad(unsigned i) { return i + (i >> LOGR); }
 
     // element index (multiplier of NT plus t) held by register slot s, for a
     // stage of radix RR
@@ -151,21 +202,44 @@ struct BlockFFT {
     __host__ __device__ static constexpr int elem_in(int s) { return slot_elem(s, first_r()); }
     __host__ __device__ static constexpr int elem_out(int s) { return slot_elem(s, LAST_R); }
 
+    // With TWQ the twiddle source is a quarter table in LDS: tw points to its
+    // real parts and the imaginary parts follow N/4+1 entries later (twlog
+    // unused).
     template <int Ns, bool INV>
-    __device__ __forceinline__ static void stage(cx<T> (&v)[PPT], T *sre, T *sim, int t,
+    __device__ __forceinline__ static void stage(cx<T> (&v)[PPT], T *sre, T *sim, unsigned t,
                                                  const cx<T> *__restrict__ tw, int twlog)
     {
         constexpr int RS = (Ns * R <= N) ? R : (N / Ns);
         constexpr int NB = PPT / RS;
         constexpr int LOGL = ilog2<Ns * RS>::value;
+        const cx<T> *tws = TWQ ? tw : opaque(tw);
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
-            const int j = t + m * NT;
-            const int jm = j & (Ns - 1);
+            const unsigned j = t + m * NT;
+            const unsigned jm = j & (Ns - 1);
             if (Ns > 1) {
+                // fetch w^1, w^2, w^4 and form the other powers by at most two
+                // products (3 table reads per butterfly instead of RS-1)
+                auto fetch = [&](unsigned e) -> cx<T> {
+                    if constexpr (TWQ) {
+                        const T *qre = reinterpret_cast<const T *>(tws);
+                        return twiddle_q<T, N, INV>(qre, qre + (N / 4 + 1), jm * e, LOGL);
+                    } else {
+                        return twiddle<T, INV>(tws, twlog, jm * e, LOGL);
+                    }
+                };
+                cx<T> w[RS > 1 ? RS : 2];
+                w[1] = fetch(1);
+                if constexpr (RS > 2) w[2] = fetch(2);
+                if constexpr (RS > 3) w[3] = mul(w[1], w[2]);
+                if constexpr (RS > 4) {
+                    w[4] = fetch(4);
+                    w[5] = mul(w[1], w[4]);
+                    w[6] = mul(w[2], w[4]);
+                    w[7] = mul(w[3], w[4]);
+                }
 #pragma unroll
-                for (int k = 1; k < RS; ++k)
-                    v[m * RS + k] = mul(v[m * RS + k], twiddle<T, INV>(tw, twlog, jm * k, LOGL));
+                for (int k = 1; k < RS; ++k) v[m * RS + k] = mul(v[m * RS + k], w[k]);
             }
             dft<T, RS, INV>::run(&v[m * RS]);
         }
@@ -173,35 +247,55 @@ struct BlockFFT {
             constexpr int NS2 = Ns * RS;
             constexpr int R2 = (NS2 * R <= N) ? R : (N / NS2);
             constexpr int NB2 = PPT / R2;
-            __syncthreads();
 #pragma unroll
-            for (int m = 0; m < NB; ++m) {
-                const int j = t + m * NT;
-                const int jm = j & (Ns - 1);
-                const int base = (j >> ilog2<Ns>::value) * Ns * RS + jm;
+            for (int part = 0; part < (XSPLIT ? 2 : 1); ++part) {
+                __syncthreads();
 #pragma unroll
-                for (int k = 0; k < RS; ++k) {
-                    const int idx = pad(base + k * Ns);
-                    sre[idx] = v[m * RS + k].re;
-                    sim[idx] = v[m * RS + k].im;
+                for (int m = 0; m < NB; ++m) {
+                    const unsigned j = t + m * NT;
+                    const unsigned jm = j & (Ns - 1);
+                    const unsigned base = (j >> ilog2<Ns>::value) * Ns * RS + jm;
+#pragma unroll
+                    for (int k = 0; k < RS; ++k) {
+                        const unsigned idx = pad(base + k * Ns);
+                        if (XSPLIT) {
+                            sre[idx] = part == 0 ? v[m * RS + k].re : v[m * RS + k].im;
+                        } else {
+                            sre[idx] = v[m * RS + k].re;
+                            sim[idx] = v[m * RS + k].im;
+                        }
+                    }
                 }
+                __syncthreads();
+                // every value of this part has been written; read the next
+                // stage's inputs (slot order m*R2 + k)
+#pragma unroll
+                for (int m = 0; m < NB2; ++m)
+#pragma unroll
+                    for (int k = 0; k < R2; ++k) {
+                        const unsigned idx = pad(t + m * NT + k * (N / R2));
+                        if (XSPLIT) {
+                            // part 0 replaces only the real fields and part 1
+                            // only the imaginary ones, so the imaginary parts
+                            // written in part 1 are still this stage's
+                            if (part == 0)
+                                v[m * R2 + k].re = sre[idx];
+                            else
+                                v[m * R2 + k].im = sre[idx];
+                        } else {
+                            v[m * R2 + k] = cx<T>{sre[idx], sim[idx]};
+                        }
+                    }
             }
-            __syncthreads();
-#pragma unroll
-            for (int m = 0; m < NB2; ++m)
-#pragma unroll
-                for (int k = 0; k < R2; ++k) {
-                    const int idx = pad(t + m * NT + k * (N / R2));
-                    v[m * R2 + k] = cx<T>{sre[idx], sim[idx]};
-                }
             stage<NS2, INV>(v, sre, sim, t, tw, twlog);
         }
     }
 
     // Transform in place.  All threads of the workgroup must call it (it
-    // contains workgroup barriers); sre/sim point to this group's LDS area.
+    // contains workgroup barriers); sre/sim point to this group's LDS area
+    // (sim unused with XSPLIT).
     template <bool INV>
-    __device__ __forceinline__ static void run(cx<T> (&v)[PPT], T *sre, T *sim, int t,
+    __device__ __forceinline__ static void run(cx<T> (&v)[PPT], T *sre, T *sim, unsigned t,
                                                const cx<T> *__restrict__ tw, int twlog)
     {
         stage<1, INV>(v, sre, sim, t, tw, twlog);

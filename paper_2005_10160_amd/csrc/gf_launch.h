@@ -29,39 +29,45 @@ struct KgenGeom {
     double t_gl4;
 };
 
-// Forward row transform (real rows of length <= px -> px/2+1 column units,
-// written transposed as out[slab][u][row]).
+// Forward row transform (real rows of length <= px -> px/2 packed column
+// units, written transposed as out[slab][u][row] with leading dimension ldc).
 //   in       base of source rows; row (b, src, y) at in + ((b*src_per_b + src)*rows + y)*row_len
 //   lin      nonzero entries per row (<= px); the rest of each row is zero
 //   rows     rows per slab; nsub slabs per batch item; nbatch items
-int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int rows, int nsub,
-                   int src_per_b, int nbatch, const RowCombo &cmb, void *out, const void *tw,
+int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int rows, int ldc,
+                   int nsub, int src_per_b, int nbatch, const RowCombo &cmb, void *out, const void *tw,
                    int twlog, hipStream_t st);
 
 // Inverse row transform: X(b,o,y)[u] = sum_split sum_i w[o][i] D[split][b][src[o][i]][u][y],
 // then real rows of length px, of which the first nx_out are written, times
 // `scale`, to out[b][o][y][x].
 int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nsplit, int nsrc,
-                   int rows, int nsub, int nbatch, const RowCombo &cmb, void *out, int nx_out,
+                   int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, void *out, int nx_out,
                    double scale, const void *tw, int twlog, hipStream_t st);
 
+// Column data are stored per slab as [unit][y] with M = px/2 units and a
+// leading dimension ldc >= ny (even, so that columns are 16-byte aligned): unit u
+// holds x-bin kx = u for u >= 1, and unit 0 packs the real-valued bins
+// kx = 0 (real part) and kx = px/2 (imaginary part).  Spectra are stored
+// [Cs][nz][M+1][py/2+1] (quarter plane, one real per frequency).
+//
 // Column pass of the forward operator: per column unit u and model b, for
 // each layer n of the split: FFT along y, multiply by conj(K^_{c,n}) and
 // accumulate over n; then inverse FFT per component.
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
-                       int U, int ny, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
 // Column pass of the adjoint: FFT of the Cs residual columns, then per layer
 // sum_c K^_{c,n} r^_c and an inverse FFT.
 int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
-                       int nz, int U, int ny, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
 // Plan time: column FFT of the row-transformed kernel fields and extraction
-// of the quarter-plane spectrum into spec[Cs][nz][U][py/2+1] (float or double).
+// of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).
 int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,
-                    int nz, int U, unsigned imag_mask, const void *tw, int twlog, hipStream_t st);
+                    int nz, int M, unsigned imag_mask, const void *tw, int twlog, hipStream_t st);
 
 // Plan time: kernel table of layers [n0, n0+nl) for the Cs components in
 // codes[], written into zeroed circulant fields E[nl][Cs][py][px] (double).
@@ -76,5 +82,12 @@ int col_forward_groups(bool fp64, int py);
 // Largest dynamic LDS allocation a workgroup may request on the current
 // device (bytes).
 size_t lds_limit();
+
+// Padded length (values) of one resident spectrum row for transform length py.
+int spec_row_pitch(bool fp64, int py);
+
+// Whether the column passes of transform length py with Cs resident
+// components fit the device's LDS.
+bool col_supported(bool fp64, int py, int Cs);
 
 }  // namespace gf

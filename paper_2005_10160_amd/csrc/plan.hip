@@ -106,7 +106,8 @@ struct gf_plan {
     unsigned mask;
     int prec;
     int max_batch;
-    int px, py, M, U, Q, twlog;
+    int px, py, M, U, Q, QP, twlog; // M column units; U = M + 1 spectral rows of QP values
+    int ldc;                        // leading dimension of column layouts (even)
     int n_out;
     int out_codes[7];
     int n_spec;
@@ -148,7 +149,7 @@ struct gf_plan {
     void fwd_split(int /*B*/, int *S, int *lps) const
     {
         const int G = gf::col_forward_groups(fp64(), py);
-        const long nblk = ((long)U + G - 1) / G;
+        const long nblk = ((long)U + G - 1) / G;   // M + 1 uniform units
         const int cap = gf::col_forward_capacity(fp64(), py, n_spec, 1);
         // cost in units of one layer of one round of resident workgroups;
         // each split adds a partial-sum write and read (~beta layers)
@@ -172,7 +173,7 @@ struct gf_plan {
     void adj_split(int B, int *S, int *lps) const
     {
         const int G = gf::col_forward_groups(fp64(), py);
-        const long nblk = ((long)U * B + G - 1) / G;
+        const long nblk = ((long)U * B + G - 1) / G;  // M + 1 uniform units
         const int cap = gf::col_forward_capacity(fp64(), py, n_spec, B);
         long s = (2L * cap + nblk - 1) / nblk;
         if (s < 1) s = 1;
@@ -187,9 +188,9 @@ struct gf_plan {
         if (op == GF_OP_FORWARD) {
             int S, l;
             fwd_split(B, &S, &l);
-            return celem() * (size_t)U * ny * ((size_t)B * nz + (size_t)S * B * n_spec);
+            return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * n_spec);
         }
-        return celem() * (size_t)U * ny * ((size_t)B * n_spec + (size_t)B * nz);
+        return celem() * (size_t)M * ldc * ((size_t)B * n_spec + (size_t)B * nz);
     }
 };
 
@@ -236,7 +237,7 @@ gf::KgenGeom kgen_geom(const gf_plan *p)
 gf_status build_spectra(gf_plan *p, hipStream_t st)
 {
     const size_t field = (size_t)p->py * p->px;
-    const size_t per_pair = field * sizeof(double) + (size_t)p->U * p->py * 2 * sizeof(double);
+    const size_t per_pair = field * sizeof(double) + (size_t)p->M * p->py * 2 * sizeof(double);
     const size_t budget = (size_t)2 << 30;
     int nl = (int)(budget / (per_pair * p->n_spec));
     if (nl < 1) nl = 1;
@@ -245,7 +246,7 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
     gf_status s;
     if ((s = hip_check(hipMalloc(&E.p, field * sizeof(double) * nl * p->n_spec), "kernel field")) != GF_OK)
         return s;
-    if ((s = hip_check(hipMalloc(&Rk.p, (size_t)p->U * p->py * 2 * sizeof(double) * nl * p->n_spec),
+    if ((s = hip_check(hipMalloc(&Rk.p, (size_t)p->M * p->py * 2 * sizeof(double) * nl * p->n_spec),
                        "kernel row spectra")) != GF_OK)
         return s;
     const gf::KgenGeom g = kgen_geom(p);
@@ -259,10 +260,10 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
             return s;
         if (gf::launch_kgen_field(E.p, nlc, n0, p->n_spec, p->spec_codes, g, gl, st) != 0)
             return fail(GF_EDEVICE, "kernel table launch failed");
-        if (gf::launch_row_r2c(true, p->px, E.p, p->px, p->px, p->py, npair, npair, 1, ident, Rk.p,
+        if (gf::launch_row_r2c(true, p->px, E.p, p->px, p->px, p->py, p->py, npair, npair, 1, ident, Rk.p,
                                p->tw64, p->twlog, st) != 0)
             return fail(GF_EDEVICE, "kernel row transform launch failed");
-        if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec, nlc, n0, p->n_spec, p->nz, p->U,
+        if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec, nlc, n0, p->n_spec, p->nz, p->M,
                                 p->imag_mask, p->tw64, p->twlog, st) != 0)
             return fail(GF_EDEVICE, "kernel column transform launch failed");
     }
@@ -346,6 +347,8 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     p->M = p->px / 2;
     p->U = p->M + 1;
     p->Q = p->py / 2 + 1;
+    p->QP = gf::spec_row_pitch(precision == GF_F64, p->py);
+    p->ldc = ny + (ny & 1);
     p->twlog = log2i(std::max(p->px, p->py));
     (void)hipGetDevice(&p->device);
 
@@ -422,7 +425,11 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
             }
         }
     }
-    p->spec_bytes = (size_t)p->n_spec * nz * p->U * p->Q * p->elem();
+    if (!gf::col_supported(p->fp64(), p->py, p->n_spec)) {
+        free_plan(p);
+        return fail(GF_EUNSUPPORTED, "transform length %d with %d components does not fit in LDS", p->py, p->n_spec);
+    }
+    p->spec_bytes = (size_t)nz * p->U * p->n_spec * p->QP * p->elem();
     if ((s = hip_check(hipMalloc(&p->spec, p->spec_bytes), "spectra")) != GF_OK) {
         free_plan(p);
         return s;
@@ -506,21 +513,21 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
     int S, lps;
     p->fwd_split(batch, &S, &lps);
     char *R = (char *)workspace;
-    char *D = R + p->celem() * (size_t)batch * p->nz * p->U * p->ny;
+    char *D = R + p->celem() * (size_t)batch * p->nz * p->M * p->ldc;
     gf::RowCombo ident{};
     ident.identity = 1;
     mark(p, GF_OP_FORWARD, 0, st);
-    if (gf::launch_row_r2c(p->fp64(), p->px, rho, p->nx, p->nx, p->ny, p->nz, p->nz, batch, ident, R,
+    if (gf::launch_row_r2c(p->fp64(), p->px, rho, p->nx, p->nx, p->ny, p->ldc, p->nz, p->nz, batch, ident, R,
                            p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 1, st);
-    if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec, D, batch, p->nz, p->U, p->ny, p->n_spec, S, lps,
+    if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec, D, batch, p->nz, p->M, p->ny, p->ldc, p->n_spec, S, lps,
                                p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 2, st);
     const double scale = kGrav / ((double)p->py * p->M);
-    if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->U * p->ny, S, p->n_spec, p->ny,
-                           p->n_out, batch, p->out_combo, d, p->nx, scale, p->tw, p->twlog, st) != 0)
+    if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->M * p->ldc, S, p->n_spec, p->ny,
+                           p->ldc, p->n_out, batch, p->out_combo, d, p->nx, scale, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 3, st);
     return GF_OK;
@@ -537,21 +544,21 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
     int S, lps;
     p->adj_split(batch, &S, &lps);
     char *R = (char *)workspace;
-    char *Gt = R + p->celem() * (size_t)batch * p->n_spec * p->U * p->ny;
+    char *Gt = R + p->celem() * (size_t)batch * p->n_spec * p->M * p->ldc;
     mark(p, GF_OP_ADJOINT, 0, st);
-    if (gf::launch_row_r2c(p->fp64(), p->px, r, p->nx, p->nx, p->ny, p->n_spec, p->n_out, batch, p->in_combo,
-                           R, p->tw, p->twlog, st) != 0)
+    if (gf::launch_row_r2c(p->fp64(), p->px, r, p->nx, p->nx, p->ny, p->ldc, p->n_spec, p->n_out, batch,
+                           p->in_combo, R, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 1, st);
-    if (gf::launch_col_adjoint(p->fp64(), p->py, R, p->spec, Gt, batch, p->nz, p->U, p->ny, p->n_spec, S, lps,
+    if (gf::launch_col_adjoint(p->fp64(), p->py, R, p->spec, Gt, batch, p->nz, p->M, p->ny, p->ldc, p->n_spec, S, lps,
                                p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 2, st);
     gf::RowCombo ident{};
     ident.identity = 1;
     const double scale = kGrav / ((double)p->py * p->M);
-    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, 0, 1, p->nz, p->ny, p->nz, batch, ident, g, p->nx, scale,
-                           p->tw, p->twlog, st) != 0)
+    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, 0, 1, p->nz, p->ny, p->ldc, p->nz, batch, ident, g, p->nx,
+                           scale, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 3, st);
     return GF_OK;
@@ -623,19 +630,25 @@ gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double 
         if (component == (1u << c)) code = c;
     const int slot = code >= 0 ? p->slot_of(code) : -1;
     if (slot < 0) return fail(GF_EINVAL, "component 0x%x has no resident spectrum", component);
-    const size_t cnt = (size_t)p->U * p->Q;
-    const size_t off = ((size_t)slot * p->nz + n) * cnt;
+    // layout [n][row][slot][QP], rows in the order kx = 0, Px/2, 1, ..., Px/2-1
+    const size_t layer = (size_t)p->U * p->n_spec * p->QP;
+    std::vector<double> lay(layer);
     gf_status s;
     if (p->fp64()) {
-        if ((s = hip_check(hipMemcpy(host_out, (const double *)p->spec + off, cnt * sizeof(double),
+        if ((s = hip_check(hipMemcpy(lay.data(), (const double *)p->spec + (size_t)n * layer, layer * sizeof(double),
                                      hipMemcpyDeviceToHost), "copy")) != GF_OK)
             return s;
     } else {
-        std::vector<float> tmp(cnt);
-        if ((s = hip_check(hipMemcpy(tmp.data(), (const float *)p->spec + off, cnt * sizeof(float),
+        std::vector<float> tmp(layer);
+        if ((s = hip_check(hipMemcpy(tmp.data(), (const float *)p->spec + (size_t)n * layer, layer * sizeof(float),
                                      hipMemcpyDeviceToHost), "copy")) != GF_OK)
             return s;
-        for (size_t i = 0; i < cnt; ++i) host_out[i] = tmp[i];
+        for (size_t i = 0; i < layer; ++i) lay[i] = tmp[i];
+    }
+    for (int kx = 0; kx <= p->M; ++kx) {
+        const int row = kx == 0 ? 0 : (kx == p->M ? 1 : kx + 1);
+        for (int ky = 0; ky < p->Q; ++ky)
+            host_out[(size_t)kx * p->Q + ky] = lay[((size_t)row * p->n_spec + slot) * p->QP + ky];
     }
     return GF_OK;
 }

@@ -62,7 +62,7 @@ class Request:
     key: GeometryKey
     op: str                       # "forward" | "adjoint"
     batch: int
-    t_arrival: float
+    t_arrival: Optional[float] = None   # scheduler clock; stamped on submit when None
     data: Any = None              # [B][nz][ny][nx] (forward) or [B][C][ny][nx] (adjoint)
     result: Any = None
     status: str = "pending"       # pending | running | done | rejected | cancelled
@@ -139,6 +139,8 @@ class Scheduler:
         return self.ex.workspace_bytes(key, op, batch) + io_bytes(key, op, batch, self.ex.elem)
 
     def submit(self, req: Request):
+        if req.t_arrival is None:
+            req.t_arrival = self.clock()
         need = self.group_bytes(req.key, req.op, req.batch) + spectra_bytes(req.key, self.ex.elem)
         if req.batch < 1 or req.batch > self.max_models or need > self.budget:
             self._finish(req, "rejected", "request needs %d bytes / %d models; budget %d bytes / %d models"
