@@ -25,20 +25,20 @@ struct ColCfg {
     static constexpr int PPT = 8;
     static constexpr int NT = N / PPT;
     static constexpr int RADIX = 8;
-    // the transform of the hot passes: split re/im exchange, LDS twiddles
-    using FFT = BlockFFT<T, N, NT, RADIX, true, true>;
+    // the transform of the hot passes: LDS twiddles
+    using FFT = BlockFFT<T, N, NT, RADIX, false, true>;
     // the plan-time transform: full exchange, global twiddles
     using FFTK = BlockFFT<T, N, NT, RADIX, false, false>;
     static constexpr int W = FFT::lds_words();
     static constexpr int VEC = 16 / (int)sizeof(T);                  // values per 16 bytes
     static constexpr int up(int x) { return ((x + VEC - 1) / VEC) * VEC; }
-    static constexpr int XW = up(W);                                  // exchange words
+    static constexpr int XW = up(2 * W);                              // exchange words (re, im)
     static constexpr int TWW = up(2 * (N / 4 + 1));                   // quarter twiddle table words
     static constexpr int QP = up(N / 2 + 1);                          // padded spectrum row
     static constexpr int CB = up(2 * (N / 2));                        // one column buffer (ldc <= N/2)
-    // T words per group: exchange, twiddles, two column buffers (forward) and
-    // two spectrum buffers of cmax rows
-    static constexpr int group_words(int cmax, bool fwd) { return XW + TWW + (fwd ? 2 * CB : 0) + 2 * cmax * QP; }
+    // T words per group: exchange, twiddles and two spectrum buffers of cmax
+    // rows (the density column of the next layer is prefetched into registers)
+    static constexpr int group_words(int cmax, bool /*fwd*/) { return XW + TWW + 2 * cmax * QP; }
     // groups (column units) per workgroup: up to 256 threads for short
     // transforms, as long as the largest variant stays within 64 KB of LDS
     static constexpr int groups()
@@ -188,7 +188,6 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     using C = ColCfg<T, N>;
     using F = typename C::FFT;
     constexpr int PPT = C::PPT, NT = C::NT, G = C::G, QP = C::QP;
-    constexpr int CB = C::CB;
     constexpr bool AS = C::ASYNC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
@@ -196,15 +195,14 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     const unsigned g = threadIdx.x / NT;
     const unsigned t = threadIdx.x % NT;
     T *xbuf = lds + (size_t)g * C::group_words(CMAX, true);
+    T *xim = xbuf + C::W;
     T *twq = xbuf + C::XW;
-    T *cbuf = twq + C::TWW;                  // two column buffers
-    T *sbuf = cbuf + 2 * CB;                 // two spectrum buffers
+    T *sbuf = twq + C::TWW;                  // two spectrum buffers
     load_quarter<T, N>(twq, twq + (N / 4 + 1), tw, twlog, t, NT);
 
     const Unit w = unit_of<NT, G>(g, M, B);
     const unsigned row = spec_row(w.uv, (unsigned)M);
     const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
-    const unsigned col_vals = 2u * (unsigned)ldc;   // ldc keeps every column 16-byte aligned
     const int split = blockIdx.y;
     const int n0 = split * lps;
     const int n1 = min(nz, n0 + lps);
@@ -216,31 +214,40 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
         for (int s = 0; s < PPT; ++s) acc[c][s] = cx<T>{T(0), T(0)};
 
+    // the density column of the next layer travels into registers, its
+    // spectrum rows into the other LDS buffer, while this layer is computed
+    cx<T> vn[PPT];
+    auto load_col = [&](int n) {
+        const cx<T> *col = column(R, (size_t)w.b * nz + n, M, w.u, ldc);
+        // unconditional loads from a clamped row (a guarded load would wait
+        // for its data at the branch join); rows past ny are zeroed on use
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            const unsigned y = t + NT * F::elem_in(s);
+            vn[s] = col[y < (unsigned)ny ? y : 0u];
+        }
+    };
     if (n0 < n1) {
-        stage_rows<T, NT, AS>(reinterpret_cast<const T *>(column(R, (size_t)w.b * nz + n0, M, w.u, ldc)), cbuf,
-                              col_vals, t);
+        load_col(n0);
         stage_rows<T, NT, AS>(spec + (size_t)n0 * layer_vals + (size_t)row * Cs * QP, sbuf, (unsigned)Cs * QP, t);
     }
     stage_wait<AS>();
 
     for (int n = n0; n < n1; ++n) {
         const int cur = (n - n0) & 1;
-        const T *ccur = cbuf + cur * CB;
         const T *scur = sbuf + cur * CMAX * QP;
-        if (n + 1 < n1) {
-            stage_rows<T, NT, AS>(reinterpret_cast<const T *>(column(R, (size_t)w.b * nz + n + 1, M, w.u, ldc)),
-                                  cbuf + (cur ^ 1) * CB, col_vals, t);
-            stage_rows<T, NT, AS>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
-                                  sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, t);
-        }
         cx<T> v[PPT];
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const unsigned y = t + NT * F::elem_in(s);
-            v[s] = cx<T>{T(0), T(0)};
-            if (y < (unsigned)ny) v[s] = take_part(cx<T>{ccur[2 * y], ccur[2 * y + 1]}, w.part);
+            v[s] = y < (unsigned)ny ? take_part(vn[s], w.part) : cx<T>{T(0), T(0)};
         }
-        F::template run<false>(v, xbuf, nullptr, t, twp, twlog);
+        if (n + 1 < n1) {
+            load_col(n + 1);
+            stage_rows<T, NT, AS>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
+                                  sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, t);
+        }
+        F::template run<false>(v, xbuf, xim, t, twp, twlog);
 #pragma unroll
         for (int c = 0; c < CMAX; ++c) {
             if (c < Cs) {
@@ -269,7 +276,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     for (int c = 0; c < CMAX; ++c) {
         if (c < Cs) {
             out_to_in<F, T, PPT>(acc[c]);
-            F::template run<true>(acc[c], xbuf, nullptr, t, twp, twlog);
+            F::template run<true>(acc[c], xbuf, xim, t, twp, twlog);
             if (w.active)
                 store_column<T, PPT, F, NT>(D + ((((size_t)split * B + w.b) * Cs + c) * M + w.u) * (size_t)ldc,
                                             acc[c], t, ny, w.part);
@@ -297,6 +304,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     const unsigned g = threadIdx.x / NT;
     const unsigned t = threadIdx.x % NT;
     T *xbuf = lds + (size_t)g * C::group_words(CMAX, false);
+    T *xim = xbuf + C::W;
     T *twq = xbuf + C::XW;
     T *sbuf = twq + C::TWW;
     load_quarter<T, N>(twq, twq + (N / 4 + 1), tw, twlog, t, NT);
@@ -314,19 +322,26 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     for (int c = 0; c < CMAX; ++c) {
 #pragma unroll
         for (int s = 0; s < PPT; ++s) rh[c][s] = cx<T>{T(0), T(0)};
-        if (c < Cs) {
+        if (c < Cs) {  // unconditional loads from clamped rows, selected after
             const cx<T> *col = column(R, (size_t)w.b * Cs + c, M, w.u, ldc);
 #pragma unroll
             for (int s = 0; s < PPT; ++s) {
                 const unsigned y = t + NT * F::elem_in(s);
-                if (y < (unsigned)ny) rh[c][s] = take_part(col[y], w.part);
+                rh[c][s] = col[y < (unsigned)ny ? y : 0u];
             }
         }
     }
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) {
+            const unsigned y = t + NT * F::elem_in(s);
+            rh[c][s] = y < (unsigned)ny ? take_part(rh[c][s], w.part) : cx<T>{T(0), T(0)};
+        }
     __syncthreads();   // twiddle table complete
 #pragma unroll
     for (int c = 0; c < CMAX; ++c)
-        if (c < Cs) F::template run<false>(rh[c], xbuf, nullptr, t, twp, twlog);
+        if (c < Cs) F::template run<false>(rh[c], xbuf, xim, t, twp, twlog);
 
     if (n0 < n1)
         stage_rows<T, NT, AS>(spec + (size_t)n0 * layer_vals + (size_t)row * Cs * QP, sbuf, (unsigned)Cs * QP, t);
@@ -363,7 +378,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
             }
         }
         out_to_in<F, T, PPT>(v);
-        F::template run<true>(v, xbuf, nullptr, t, twp, twlog);
+        F::template run<true>(v, xbuf, xim, t, twp, twlog);
         if (w.active)
             store_column<T, PPT, F, NT>(Gout + (((size_t)w.b * nz + n) * M + w.u) * (size_t)ldc, v, t, ny, w.part);
         stage_wait<AS>();

@@ -176,8 +176,18 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog
 // entries; with XSPLIT = true one array, through which the real and the
 // imaginary parts are exchanged one after the other (half the LDS, twice the
 // barriers).  Indices are padded by one word every R to spread banks.
-template <typename T, int N, int NT, int R, bool XSPLIT = false, bool TWQ = false>
+// With WAVESYNC (a group of exactly one wave) the exchanges are ordered by
+// waiting for this wave's own LDS operations instead of a workgroup barrier.
+template <typename T, int N, int NT, int R, bool XSPLIT = false, bool TWQ = false, bool WAVESYNC = false>
 struct BlockFFT {
+    static_assert(!WAVESYNC || NT == 64, "wave-local exchange needs one wave per transform");
+    __device__ __forceinline__ static void xsync()
+    {
+        if constexpr (WAVESYNC)
+            asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        else
+            __syncthreads();
+    }
     static constexpr int PPT = N / NT;
     static constexpr int LOGN = ilog2<N>::value;
     static constexpr int LOGR = ilog2<R>::value;
@@ -249,7 +259,7 @@ struct BlockFFT {
             constexpr int NB2 = PPT / R2;
 #pragma unroll
             for (int part = 0; part < (XSPLIT ? 2 : 1); ++part) {
-                __syncthreads();
+                xsync();
 #pragma unroll
                 for (int m = 0; m < NB; ++m) {
                     const unsigned j = t + m * NT;
@@ -266,7 +276,7 @@ struct BlockFFT {
                         }
                     }
                 }
-                __syncthreads();
+                xsync();
                 // every value of this part has been written; read the next
                 // stage's inputs (slot order m*R2 + k)
 #pragma unroll

@@ -18,6 +18,33 @@
 
 namespace gf {
 
+// The combination that feeds (forward) or reads (inverse) sub-row o: up to
+// two sources with weights.  The selection runs over static indices, so the
+// combination table stays in scalar registers instead of being fetched from
+// memory per lane.
+template <typename T>
+struct Term {
+    int n, s0, s1;
+    T w0, w1;
+};
+
+template <typename T>
+__device__ __forceinline__ Term<T> combo_term(const RowCombo &cmb, int o)
+{
+    Term<T> r{1, o, o, T(1), T(0)};
+    if (cmb.identity) return r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (o == k) {
+            r.n = cmb.nterm[k];
+            r.s0 = cmb.src[k][0];
+            r.s1 = cmb.nterm[k] > 1 ? cmb.src[k][1] : cmb.src[k][0];
+            r.w0 = cmb.nterm[k] > 0 ? (T)cmb.w[k][0] : T(0);
+            r.w1 = cmb.nterm[k] > 1 ? (T)cmb.w[k][1] : T(0);
+        }
+    return r;
+}
+
 // Forward rows: 16 points a lane for long rows, real and imaginary parts
 // exchanged one after the other through one LDS array per row; rows per
 // workgroup chosen so that the transposed stores are 128-byte segments
@@ -27,7 +54,7 @@ struct RowCfgF {
     static constexpr int PPT = (M >= 1024) ? 16 : ((M >= 8) ? 8 : M);
     static constexpr int NT = M / PPT;
     static constexpr int RADIX = PPT >= 8 ? 8 : PPT;
-    using FFT = BlockFFT<T, M, NT, RADIX, true, false>;
+    using FFT = BlockFFT<T, M, NT, RADIX, true, false, NT == 64>;
     static constexpr int W = FFT::lds_words();
     // row stride = 4 mod 64 words: the transposed reads (16 rows x 4 units per
     // wave) then fall in distinct banks
@@ -88,32 +115,63 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
         const int b = (int)(gr / per_b);
         const int s = (int)((gr / rows) % nsub);
         const int y = (int)(gr % rows);
-        int nterm = 1;
-        int src0 = s, src1 = 0;
-        T w0 = T(1), w1 = T(0);
-        if (!cmb.identity) {
-            nterm = cmb.nterm[s];
-            src0 = cmb.src[s][0];
-            src1 = cmb.src[s][1];
-            w0 = (T)cmb.w[s][0];
-            w1 = (T)cmb.w[s][1];
-        }
+        const Term<T> tm = combo_term<T>(cmb, s);
+        const int nterm = tm.n, src0 = tm.s0, src1 = tm.s1;
+        const T w0 = tm.w0, w1 = tm.w1;
         const T *r0 = in + (((long)b * src_per_b + src0) * rows + y) * row_len;
         const T *r1 = in + (((long)b * src_per_b + src1) * rows + y) * row_len;
+        // Loads are unconditional (indices clamped into the row, values
+        // selected afterwards): a guarded load would wait for its data at the
+        // branch join and serialise the row.
+        const bool pairs = nterm == 1 && ((row_len | lin) & 1) == 0 &&
+                           ((reinterpret_cast<size_t>(in) & (2 * sizeof(T) - 1)) == 0);
+        if (pairs) {  // (x[2j], x[2j+1]) as one vector
+            cx<T> pr[PPT];
 #pragma unroll
-        for (int sl = 0; sl < PPT; ++sl) {
-            const unsigned j = t + NT * F::elem_in(sl);
-            const unsigned x0 = 2 * j, x1 = 2 * j + 1;
-            T re = T(0), im = T(0);
-            if (nterm > 0) {
-                if (x0 < (unsigned)lin) re = w0 * r0[x0];
-                if (x1 < (unsigned)lin) im = w0 * r0[x1];
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_in(sl);
+                pr[sl] = *reinterpret_cast<const cx<T> *>(r0 + 2 * (2 * j < (unsigned)lin ? j : 0u));
+            }
+#pragma unroll
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_in(sl);
+                v[sl] = 2 * j < (unsigned)lin ? cx<T>{w0 * pr[sl].re, w0 * pr[sl].im} : cx<T>{T(0), T(0)};
+            }
+        } else {
+            T e0[PPT], o0[PPT];
+#pragma unroll
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_in(sl);
+                const unsigned x0 = 2 * j, x1 = 2 * j + 1;
+                e0[sl] = r0[x0 < (unsigned)lin ? x0 : 0u];
+                o0[sl] = r0[x1 < (unsigned)lin ? x1 : 0u];
             }
             if (nterm > 1) {
-                if (x0 < (unsigned)lin) re += w1 * r1[x0];
-                if (x1 < (unsigned)lin) im += w1 * r1[x1];
+                T e1[PPT], o1[PPT];
+#pragma unroll
+                for (int sl = 0; sl < PPT; ++sl) {
+                    const unsigned j = t + NT * F::elem_in(sl);
+                    const unsigned x0 = 2 * j, x1 = 2 * j + 1;
+                    e1[sl] = r1[x0 < (unsigned)lin ? x0 : 0u];
+                    o1[sl] = r1[x1 < (unsigned)lin ? x1 : 0u];
+                }
+#pragma unroll
+                for (int sl = 0; sl < PPT; ++sl) {
+                    e0[sl] = w0 * e0[sl] + w1 * e1[sl];
+                    o0[sl] = w0 * o0[sl] + w1 * o1[sl];
+                }
+            } else {
+#pragma unroll
+                for (int sl = 0; sl < PPT; ++sl) {
+                    e0[sl] *= w0;
+                    o0[sl] *= w0;
+                }
             }
-            v[sl] = cx<T>{re, im};
+#pragma unroll
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_in(sl);
+                v[sl] = cx<T>{2 * j < (unsigned)lin ? e0[sl] : T(0), 2 * j + 1 < (unsigned)lin ? o0[sl] : T(0)};
+            }
         }
     } else {
 #pragma unroll
@@ -185,45 +243,73 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
 
-    const long gr0 = (long)blockIdx.x * TR;
-    // gather X(row)[u] transposed: consecutive lanes read consecutive rows
-    for (unsigned it = threadIdx.x; it < (unsigned)(M * TR); it += C::THREADS) {
-        const unsigned r = it % TR;
-        const unsigned u = it / TR;
-        const long grr = gr0 + r;
-        cx<T> acc{T(0), T(0)};
-        if (grr < nrows_total) {
-            const long per_b = (long)nsub * rows;
-            const int b = (int)(grr / per_b);
-            const int o = (int)((grr / rows) % nsub);
-            const int y = (int)(grr % rows);
-            int nterm = 1;
-            int srcs[2] = {o, 0};
-            T ws[2] = {T(1), T(0)};
-            if (!cmb.identity) {
-                nterm = cmb.nterm[o];
-                srcs[0] = cmb.src[o][0];
-                srcs[1] = cmb.src[o][1];
-                ws[0] = (T)cmb.w[o][0];
-                ws[1] = (T)cmb.w[o][1];
-            }
-            for (int sp = 0; sp < nsplit; ++sp)
-                for (int i = 0; i < nterm; ++i) {
-                    const cx<T> x = D[sp * split_stride + (((long)b * nsrc + srcs[i]) * M + u) * (long)ldc + y];
-                    acc = add(acc, scale(x, ws[i]));
-                }
+    // Row groups in XCD-contiguous order: the hardware deals consecutive
+    // blocks to the eight XCDs in turn, while neighbouring row groups share
+    // the 128-byte lines of the gather below; giving each XCD a contiguous
+    // range keeps those shared lines in one L2.
+    const unsigned nb = gridDim.x, xcd = blockIdx.x % 8u, k = blockIdx.x / 8u;
+    const unsigned q = nb / 8u, rem = nb % 8u;
+    const long gr0 = (long)(xcd * q + min(xcd, rem) + k) * TR;
+
+    // gather X(row)[u] transposed (consecutive lanes read consecutive rows),
+    // summing the per-split partials.  Thread item i covers row
+    // threadIdx.x % TR (the same for every item, as THREADS = TR * NT) and
+    // unit threadIdx.x / TR + i * NT.
+    bool two = false;   // some output combines two spectra (gzz)
+    if (!cmb.identity)
+#pragma unroll
+        for (int o = 0; o < 8; ++o) two |= o < nsub && cmb.nterm[o] > 1;
+    const unsigned r0 = threadIdx.x % TR, u0 = threadIdx.x / TR;
+    long off0, off1;
+    T wa, wb;
+    {
+        const long grr = gr0 + r0;
+        const bool valid = grr < nrows_total;
+        const long gc = valid ? grr : 0;
+        const long per_b = (long)nsub * rows;
+        const int b = (int)(gc / per_b);
+        const int o = (int)((gc / rows) % nsub);
+        const int y = (int)(gc % rows);
+        const Term<T> tm = combo_term<T>(cmb, o);
+        wa = valid ? tm.w0 : T(0);
+        wb = valid ? tm.w1 : T(0);
+        off0 = (((long)b * nsrc + tm.s0) * M + u0) * (long)ldc + y;
+        off1 = (((long)b * nsrc + tm.s1) * M + u0) * (long)ldc + y;
+    }
+    const long ustep = (long)NT * ldc;
+    cx<T> acc[PPT];
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) acc[i] = cx<T>{T(0), T(0)};
+    for (int sp = 0; sp < nsplit; ++sp) {
+        const cx<T> *D0 = D + sp * split_stride + off0;
+        cx<T> x0[PPT];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) x0[i] = D0[i * ustep];
+        if (two) {
+            const cx<T> *D1 = D + sp * split_stride + off1;
+            cx<T> x1[PPT];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) x1[i] = D1[i * ustep];
+#pragma unroll
+            for (int i = 0; i < PPT; ++i) acc[i] = add(acc[i], scale(x1[i], wb));
         }
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) acc[i] = add(acc[i], scale(x0[i], wa));
+    }
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+        const unsigned r = r0, u = u0 + i * NT;
         T *qre = lds + (size_t)r * 2 * W;
         T *qim = qre + W;
         if (u == 0) {  // packed: X[0] = re, X[M] = im, both real
-            qre[0] = acc.re;
+            qre[0] = acc[i].re;
             qim[0] = T(0);
-            qre[F::pad(M)] = acc.im;
+            qre[F::pad(M)] = acc[i].im;
             qim[F::pad(M)] = T(0);
         } else {
             const unsigned idx = F::pad(u);
-            qre[idx] = acc.re;
-            qim[idx] = acc.im;
+            qre[idx] = acc[i].re;
+            qim[idx] = acc[i].im;
         }
     }
     __syncthreads();
