@@ -33,7 +33,7 @@ struct ColCfg {
     static constexpr int VEC = 16 / (int)sizeof(T);                  // values per 16 bytes
     static constexpr int up(int x) { return ((x + VEC - 1) / VEC) * VEC; }
     static constexpr int XW = up(2 * W);                              // exchange words (re, im)
-    static constexpr int TWW = up(2 * (N / 4 + 1));                   // quarter twiddle table words
+    static constexpr int TWW = up(2 * FFT::stw_entries());            // per-stage twiddle table words
     static constexpr int QP = up(N / 2 + 1);                          // padded spectrum row
     static constexpr int CB = up(2 * (N / 2));                        // one column buffer (ldc <= N/2)
     // T words per group: exchange, twiddles and two spectrum buffers of cmax
@@ -198,7 +198,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     T *xim = xbuf + C::W;
     T *twq = xbuf + C::XW;
     T *sbuf = twq + C::TWW;                  // two spectrum buffers
-    load_quarter<T, N>(twq, twq + (N / 4 + 1), tw, twlog, t, NT);
+    F::load_stage_table(twq, tw, twlog, t, NT);
 
     const Unit w = unit_of<NT, G>(g, M, B);
     const unsigned row = spec_row(w.uv, (unsigned)M);
@@ -216,15 +216,17 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 
     // the density column of the next layer travels into registers, its
     // spectrum rows into the other LDS buffer, while this layer is computed
-    cx<T> vn[PPT];
+    cx<T> vn[PPT] = {};
     auto load_col = [&](int n) {
         const cx<T> *col = column(R, (size_t)w.b * nz + n, M, w.u, ldc);
         // unconditional loads from a clamped row (a guarded load would wait
-        // for its data at the branch join); rows past ny are zeroed on use
+        // for its data at the branch join); rows past ny are zeroed on use.
+        // Slots in the upper half (y >= N/2 >= ny) are the embedding's zero
+        // padding and are never loaded.
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const unsigned y = t + NT * F::elem_in(s);
-            vn[s] = col[y < (unsigned)ny ? y : 0u];
+            if (F::elem_in(s) < PPT / 2) vn[s] = col[y < (unsigned)ny ? y : 0u];
         }
     };
     if (n0 < n1) {
@@ -240,7 +242,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const unsigned y = t + NT * F::elem_in(s);
-            v[s] = y < (unsigned)ny ? take_part(vn[s], w.part) : cx<T>{T(0), T(0)};
+            v[s] = (F::elem_in(s) < PPT / 2 && y < (unsigned)ny) ? take_part(vn[s], w.part) : cx<T>{T(0), T(0)};
         }
         if (n + 1 < n1) {
             load_col(n + 1);
@@ -307,7 +309,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     T *xim = xbuf + C::W;
     T *twq = xbuf + C::XW;
     T *sbuf = twq + C::TWW;
-    load_quarter<T, N>(twq, twq + (N / 4 + 1), tw, twlog, t, NT);
+    F::load_stage_table(twq, tw, twlog, t, NT);
     const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
 
     const Unit w = unit_of<NT, G>(g, M, B);
@@ -327,7 +329,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
             for (int s = 0; s < PPT; ++s) {
                 const unsigned y = t + NT * F::elem_in(s);
-                rh[c][s] = col[y < (unsigned)ny ? y : 0u];
+                if (F::elem_in(s) < PPT / 2) rh[c][s] = col[y < (unsigned)ny ? y : 0u];   // upper half: padding
             }
         }
     }
@@ -336,7 +338,8 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const unsigned y = t + NT * F::elem_in(s);
-            rh[c][s] = y < (unsigned)ny ? take_part(rh[c][s], w.part) : cx<T>{T(0), T(0)};
+            rh[c][s] = (F::elem_in(s) < PPT / 2 && y < (unsigned)ny) ? take_part(rh[c][s], w.part)
+                                                                       : cx<T>{T(0), T(0)};
         }
     __syncthreads();   // twiddle table complete
 #pragma unroll
@@ -513,7 +516,8 @@ int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void 
                        int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
-    if (Cs < 1 || Cs > 6) return -2;
+    // the kernels skip the upper half of each column (zero padding)
+    if (Cs < 1 || Cs > 6 || ny < 1 || 2 * ny > py || ldc < ny) return -2;
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
         return fp64 ? fwd_c<double, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, imag_mask,    \
@@ -532,7 +536,7 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
                        int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
-    if (Cs < 1 || Cs > 6) return -2;
+    if (Cs < 1 || Cs > 6 || ny < 1 || 2 * ny > py || ldc < ny) return -2;   // upper half of columns skipped
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
         return fp64 ? adj_c<double, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, imag_mask, \

@@ -122,39 +122,6 @@ __device__ __forceinline__ const cx<T> *opaque(const cx<T> *p)
     return p;
 }
 
-// Twiddles of a length-N transform from a quarter-wave table in LDS,
-// q[r] = exp(-2 pi i r / N) for r in [0, N/4]:  exp(-2 pi i m / N) =
-// q[m mod N/4] * (-i)^(m div N/4).
-template <typename T, int N, bool INV>
-__device__ __forceinline__ cx<T> twiddle_q(const T *qre, const T *qim, unsigned a, int logL)
-{
-    constexpr int LOGN = ilog2<N>::value;
-    const unsigned m = (a << (unsigned)(LOGN - logL)) & (N - 1);
-    const unsigned r = m & (N / 4 - 1);
-    const unsigned q = m >> (LOGN - 2);
-    const T c = qre[r], s = qim[r];
-    cx<T> w;
-    switch (q) {
-    case 0: w = cx<T>{c, s}; break;
-    case 1: w = cx<T>{s, -c}; break;      // times -i
-    case 2: w = cx<T>{-c, -s}; break;     // times -1
-    default: w = cx<T>{-s, c}; break;     // times +i
-    }
-    return INV ? conjg(w) : w;
-}
-
-// Fill the quarter table of length N from the global table (length 2^twlog).
-template <typename T, int N>
-__device__ __forceinline__ void load_quarter(T *qre, T *qim, const cx<T> *__restrict__ tw, int twlog,
-                                             unsigned tid, unsigned nthreads)
-{
-    constexpr int LOGN = ilog2<N>::value;
-    for (unsigned r = tid; r <= N / 4; r += nthreads) {
-        const cx<T> w = tw[r << (unsigned)(twlog - LOGN)];
-        qre[r] = w.re;
-        qim[r] = w.im;
-    }
-}
 template <typename T, bool INV>
 __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog, unsigned a, int logL)
 {
@@ -175,10 +142,11 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog
 // LDS per group: with XSPLIT = false, two arrays (re, im) of lds_words()
 // entries; with XSPLIT = true one array, through which the real and the
 // imaginary parts are exchanged one after the other (half the LDS, twice the
-// barriers).  Indices are padded by one word every R to spread banks.
+// barriers).  Exchange indices are padded per stage (see xpad) to avoid bank
+// conflicts.
 // With WAVESYNC (a group of exactly one wave) the exchanges are ordered by
 // waiting for this wave's own LDS operations instead of a workgroup barrier.
-template <typename T, int N, int NT, int R, bool XSPLIT = false, bool TWQ = false, bool WAVESYNC = false>
+template <typename T, int N, int NT, int R, bool XSPLIT = false, bool TWS = false, bool WAVESYNC = false>
 struct BlockFFT {
     static_assert(!WAVESYNC || NT == 64, "wave-local exchange needs one wave per transform");
     __device__ __forceinline__ static void xsync()
@@ -196,10 +164,50 @@ struct BlockFFT {
     static constexpr int LAST_R = (LOGN % LOGR == 0) ? R : (1 << (LOGN % LOGR));
     static constexpr int NSTAGES = (LOGN + LOGR - 1) / LOGR;
 
-    __host__ __device__ static constexpr int lds_words() { return N + N / R + 1; }
+    // LDS layout of the exchange that follows a stage of span Ns and radix
+    // RS.  The stage writes element base + k Ns (k < RS) and the next stage
+    // reads consecutive elements.  A padding of c words every 2^P elements
+    // keeps both access patterns free of LDS bank conflicts (64 banks of 4
+    // bytes, 256 bytes a cycle): after span 1 (a stride of RS elements across
+    // lanes) one word every 256 bytes; after spans 1 < Ns < 64 (runs of Ns
+    // lanes) Ns words every butterfly group of Ns RS elements; spans of 64
+    // and more write whole rows and need none.  The padding is additive, so
+    // constant offsets still fold into the instructions' immediates.
+    static constexpr int LOGE = ilog2<256 / sizeof(T)>::value;  // elements a bank row
+    __host__ __device__ static constexpr int xpad_words(int ns) { return ns == 1 ? 1 : (ns >= 64 ? 0 : ns); }
+    __host__ __device__ static constexpr int xpad_shift(int ns, int rs)
+    {
+        int p = 0;
+        for (int x = ns * rs; x > 1; x >>= 1) ++p;
+        return ns == 1 ? LOGE : p;
+    }
+    template <int Ns, int RS>
+    __device__ __forceinline__ static unsigned xpad(unsigned i)
+    {
+        constexpr int c = xpad_words(Ns), p = xpad_shift(Ns, RS);
+        if constexpr (c == 0)
+            return i;
+        else
+            return i + c * (i >> p);
+    }
+    // T words of one exchange array: the largest padded index of any exchange
+    __host__ __device__ static constexpr int lds_words()
+    {
+        int w = N;
+        int ns = 1, rs = (N >= R ? R : N);
+        while (ns * rs < N) {
+            const int e = N + xpad_words(ns) * ((N - 1) >> xpad_shift(ns, rs));
+            if (e > w) w = e;
+            ns *= rs;
+            rs = (ns * R <= N) ? R : N / ns;
+        }
+        return w;
+    }
     // T words of LDS one group needs
     __host__ __device__ static constexpr int lds_group_words() { return (XSPLIT ? 1 : 2) * lds_words(); }
-    __device__ __forceinline__ static unsigned pad(unsigned i) { return i + (i >> LOGR); }
+    // layout of data handed to or taken from the transform through LDS by
+    // callers: element i at word i
+    __device__ __forceinline__ static unsigned pad(unsigned i) { return i; }
 
     // element index (multiplier of NT plus t) held by register slot s, for a
     // stage of radix RR
@@ -212,9 +220,39 @@ struct BlockFFT {
     __host__ __device__ static constexpr int elem_in(int s) { return slot_elem(s, first_r()); }
     __host__ __device__ static constexpr int elem_out(int s) { return slot_elem(s, LAST_R); }
 
-    // With TWQ the twiddle source is a quarter table in LDS: tw points to its
-    // real parts and the imaginary parts follow N/4+1 entries later (twlog
-    // unused).
+    // Per-stage twiddle table (TWS): for every stage of span Ns > 1 the Ns
+    // values W(jm, Ns RS), jm < Ns, stored one stage after the other, real
+    // parts then imaginary parts.  Lanes of a stage read consecutive entries
+    // (no LDS bank conflicts); the other powers are formed by products.
+    __host__ __device__ static constexpr int stage_radix(int Ns) { return (Ns * R <= N) ? R : N / Ns; }
+    __host__ __device__ static constexpr int stw_offset(int Ns)
+    {
+        int off = 0;
+        for (int s = R; s < Ns; s *= R) off += s;
+        return off;
+    }
+    __host__ __device__ static constexpr int stw_entries() { return stw_offset(N); }
+
+    // Fill the per-stage table (tre: stw_entries() real parts, then as many
+    // imaginary parts) from the global table of length 2^twlog.
+    __device__ static void load_stage_table(T *tre, const cx<T> *__restrict__ tw, int twlog, unsigned tid,
+                                            unsigned nthreads)
+    {
+        T *tim = tre + stw_entries();
+        for (unsigned i = tid; i < (unsigned)stw_entries(); i += nthreads) {
+            unsigned ns = R, off = 0;
+            while (i >= off + ns) {
+                off += ns;
+                ns *= R;
+            }
+            const unsigned len = ns * (unsigned)stage_radix((int)ns);
+            const cx<T> w = tw[(i - off) << (unsigned)(twlog - __builtin_ctz(len))];
+            tre[i] = w.re;
+            tim[i] = w.im;
+        }
+    }
+
+    // With TWS, tw points to the per-stage table in LDS (twlog unused).
     template <int Ns, bool INV>
     __device__ __forceinline__ static void stage(cx<T> (&v)[PPT], T *sre, T *sim, unsigned t,
                                                  const cx<T> *__restrict__ tw, int twlog)
@@ -222,28 +260,30 @@ struct BlockFFT {
         constexpr int RS = (Ns * R <= N) ? R : (N / Ns);
         constexpr int NB = PPT / RS;
         constexpr int LOGL = ilog2<Ns * RS>::value;
-        const cx<T> *tws = TWQ ? tw : opaque(tw);
+        const cx<T> *tws = TWS ? tw : opaque(tw);
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
             const unsigned j = t + m * NT;
             const unsigned jm = j & (Ns - 1);
             if (Ns > 1) {
-                // fetch w^1, w^2, w^4 and form the other powers by at most two
-                // products (3 table reads per butterfly instead of RS-1)
-                auto fetch = [&](unsigned e) -> cx<T> {
-                    if constexpr (TWQ) {
-                        const T *qre = reinterpret_cast<const T *>(tws);
-                        return twiddle_q<T, N, INV>(qre, qre + (N / 4 + 1), jm * e, LOGL);
-                    } else {
-                        return twiddle<T, INV>(tws, twlog, jm * e, LOGL);
-                    }
-                };
                 cx<T> w[RS > 1 ? RS : 2];
-                w[1] = fetch(1);
-                if constexpr (RS > 2) w[2] = fetch(2);
+                if constexpr (TWS) {
+                    const T *tre = reinterpret_cast<const T *>(tws);
+                    constexpr int off = stw_offset(Ns);
+                    w[1] = cx<T>{tre[off + jm], tre[stw_entries() + off + jm]};
+                    if (INV) w[1] = conjg(w[1]);
+                    if constexpr (RS > 2) w[2] = mul(w[1], w[1]);
+                    if constexpr (RS > 4) w[4] = mul(w[2], w[2]);
+                } else {
+                    // fetch w^1, w^2, w^4 and form the other powers by at
+                    // most two products (3 table reads per butterfly instead
+                    // of RS-1)
+                    w[1] = twiddle<T, INV>(tws, twlog, jm, LOGL);
+                    if constexpr (RS > 2) w[2] = twiddle<T, INV>(tws, twlog, jm * 2, LOGL);
+                    if constexpr (RS > 4) w[4] = twiddle<T, INV>(tws, twlog, jm * 4, LOGL);
+                }
                 if constexpr (RS > 3) w[3] = mul(w[1], w[2]);
                 if constexpr (RS > 4) {
-                    w[4] = fetch(4);
                     w[5] = mul(w[1], w[4]);
                     w[6] = mul(w[2], w[4]);
                     w[7] = mul(w[3], w[4]);
@@ -267,7 +307,7 @@ struct BlockFFT {
                     const unsigned base = (j >> ilog2<Ns>::value) * Ns * RS + jm;
 #pragma unroll
                     for (int k = 0; k < RS; ++k) {
-                        const unsigned idx = pad(base + k * Ns);
+                        const unsigned idx = xpad<Ns, RS>(base + k * Ns);
                         if (XSPLIT) {
                             sre[idx] = part == 0 ? v[m * RS + k].re : v[m * RS + k].im;
                         } else {
@@ -283,7 +323,7 @@ struct BlockFFT {
                 for (int m = 0; m < NB2; ++m)
 #pragma unroll
                     for (int k = 0; k < R2; ++k) {
-                        const unsigned idx = pad(t + m * NT + k * (N / R2));
+                        const unsigned idx = xpad<Ns, RS>(t + m * NT + k * (N / R2));
                         if (XSPLIT) {
                             // part 0 replaces only the real fields and part 1
                             // only the imaginary ones, so the imaginary parts

@@ -77,8 +77,15 @@ struct RowCfg {
     static constexpr int NT = M / PPT;
     static constexpr int RADIX = PPT;
     using FFT = BlockFFT<T, M, NT, RADIX>;
-    static constexpr int W = FFT::lds_words();
-    static constexpr int ROW_BYTES = 2 * W * (int)sizeof(T);
+    // one word beyond the transform's arrays: element M holds the packed
+    // Nyquist bin X[M] before the half-length spectrum is formed
+    static constexpr int W = FFT::lds_words() + 1;
+    // row stride (re and im arrays) = 8 mod the elements of one 256-byte bank
+    // row: the transposed gather (rows fastest, 8 units a wave) then hits
+    // distinct banks
+    static constexpr int E = 256 / (int)sizeof(T);
+    static constexpr int RWS = 2 * W + ((E + 8 - (2 * W) % E) % E);
+    static constexpr int ROW_BYTES = RWS * (int)sizeof(T);
     // rows per workgroup: a power of two within 80 KB of LDS (two workgroups
     // per CU) and 1024 threads
     static constexpr int tr_calc()
@@ -299,7 +306,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const unsigned r = r0, u = u0 + i * NT;
-        T *qre = lds + (size_t)r * 2 * W;
+        T *qre = lds + (size_t)r * C::RWS;
         T *qim = qre + W;
         if (u == 0) {  // packed: X[0] = re, X[M] = im, both real
             qre[0] = acc[i].re;
@@ -317,7 +324,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     const unsigned g = threadIdx.x / NT;
     const unsigned t = threadIdx.x % NT;
     const long gr = gr0 + g;
-    T *sre = lds + (size_t)g * 2 * W;
+    T *sre = lds + (size_t)g * C::RWS;
     T *sim = sre + W;
     const int logpx = ilog2<2 * M>::value;
 

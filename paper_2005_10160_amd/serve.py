@@ -69,6 +69,7 @@ class Request:
     error: Optional[str] = None
     t_admit: Optional[float] = None
     t_done: Optional[float] = None
+    keep_result: bool = True      # False: the output buffer is recycled once done (load replay)
     event: threading.Event = field(default_factory=threading.Event, repr=False)
 
     @property
@@ -284,6 +285,9 @@ class GpuExecutor:
         self.events = [None] * n_slots
         self.keep = [None] * n_slots
         self.lock = threading.Lock()
+        # pinned output buffers of requests that do not keep their result,
+        # by shape, for reuse
+        self.out_pool = collections.defaultdict(list)
 
     def plan_for(self, key):
         p = self.plans.get(key)
@@ -341,17 +345,25 @@ class GpuExecutor:
             o = 0
             for r in reqs:
                 if r.result is None:
-                    r.result = torch.empty((r.batch,) + shape_out[1:], dtype=self.dtype, pin_memory=True)
+                    shp = (r.batch,) + shape_out[1:]
+                    free = self.out_pool.get(shp)
+                    r.result = free.pop() if free else torch.empty(shp, dtype=self.dtype, pin_memory=True)
                 r.result.copy_(y[o:o + r.batch], non_blocking=True)
                 o += r.batch
             ev = torch.cuda.Event()
             ev.record(st)
         self.events[slot] = ev
-        self.keep[slot] = (x, y, ws)
+        self.keep[slot] = (x, y, ws, reqs)
 
     def poll(self, slot):
         ev = self.events[slot]
         if ev is None or ev.query():
+            kept = self.keep[slot]
+            if kept is not None:
+                for r in kept[3]:
+                    if not r.keep_result and r.result is not None:
+                        self.out_pool[tuple(r.result.shape)].append(r.result)
+                        r.result = None
             self.events[slot] = None
             self.keep[slot] = None
             return True
@@ -423,22 +435,24 @@ def _percentiles(vals):
 
 
 def make_inputs(trace, precision, device="cuda:0"):
-    """Pinned host inputs for a trace: one buffer per (shape, batch) is drawn
-    once (seeded) and shared by the requests that need it."""
+    """Pinned host inputs for a trace: one buffer of the trace's largest batch
+    per (grid, operation) is drawn once (seeded); each request takes the
+    leading models of it."""
     import torch
     dt = torch.float32 if precision == "f32" else torch.float64
+    bmax = max(tr.batch for tr in trace)
     pool = {}
     gen = torch.Generator().manual_seed(500)
     out = []
     for tr in trace:
         C = 6 if tr.full_tensor else 1
-        shape = (tr.batch, tr.nz, tr.n, tr.n) if tr.op == "forward" else (tr.batch, C, tr.n, tr.n)
+        shape = (bmax, tr.nz, tr.n, tr.n) if tr.op == "forward" else (bmax, C, tr.n, tr.n)
         k = (shape, tr.op)
         if k not in pool:
             t = torch.empty(shape, dtype=dt, pin_memory=True)
             t.copy_(torch.rand(shape, generator=gen, dtype=torch.float64).sub_(0.5).mul_(1000.0))
             pool[k] = t
-        out.append(pool[k])
+        out.append(pool[k][:tr.batch])
     return out
 
 
@@ -462,7 +476,7 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
         if delay > 0:
             time.sleep(delay)
         if batched:
-            r = Request(tr.rid, key, tr.op, tr.batch, time.perf_counter(), x)
+            r = Request(tr.rid, key, tr.op, tr.batch, time.perf_counter(), x, keep_result=False)
             srv.submit(r)
             reqs.append([r])
         else:
@@ -470,7 +484,7 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
             t_arr = time.perf_counter()
             parts = []
             for b in range(tr.batch):
-                r = Request(tr.rid * 100 + b, key, tr.op, 1, t_arr, x[b:b + 1])
+                r = Request(tr.rid * 100 + b, key, tr.op, 1, t_arr, x[b:b + 1], keep_result=False)
                 srv.submit(r)
                 parts.append(r)
             reqs.append(parts)
