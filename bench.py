@@ -13,8 +13,10 @@ the number of kernel-matrix entries the operator applies per second
 
 One JSON line is printed.  Besides the headline FP64 forward it carries the
 FP32 path, the adjoint, a live roofline of the dominant kernel (the column
-pass), the CPU oracle timed on a bounded sample, and (with --serve-seconds)
-a short served-latency run.
+pass), the CPU oracle timed on a bounded sample, and a served-latency run:
+a seeded Poisson trace of mixed requests (3 s at 200 req/s by default)
+replayed through the FP32 continuous-batching server and through the plain
+FP64 operator (FIFO, one model per call), each with p50/p99 latency.
 """
 
 import argparse
@@ -132,7 +134,8 @@ def main():
     ap.add_argument("--cpu-stations", type=int, default=2)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=0.0)
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="length of the replayed request trace (0: no serving run)")
     ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (read 1 GiB, write 1 GiB) so that "

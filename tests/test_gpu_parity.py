@@ -278,3 +278,55 @@ def test_paper_scale_sampled(gf, orc, prec, tol):
         e = rel(gv, want[:, c])
         note("paper scale %s %s sampled rel %.2e" % (prec, NAMES[c], e))
         assert e <= tol, NAMES[c]
+
+
+# every transform length the library instantiates: nx (ny) = 2^k + 1 makes
+# the circulant length Px (Py) = 4 * 2^k, so these pairs reach row lengths
+# Px/2 = 8 ... 2048 and column lengths Py = 16 ... 4096
+SWEEP = [(9, 5), (5, 9), (33, 17), (17, 33), (129, 65), (65, 129), (513, 257), (257, 513),
+         (1025, 3), (3, 1025)]
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+@pytest.mark.parametrize("nx,ny", SWEEP)
+def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
+    """Forward and adjoint at every row and column transform length against
+    the direct sum at sampled stations (corners, centre, an off-centre
+    station; nz = 3, all seven components).  The FP64 column pass of length
+    4096 does not fit in LDS: its plan must fail with GF_EUNSUPPORTED."""
+    from paper_2005_10160_amd import _native
+    g = Geometry(nx, ny, 3, 20.0, 25.0, 15.0, 7.0)
+    rng = np.random.default_rng(nx * 7919 + ny)
+    rho = rng.uniform(-500.0, 500.0, size=(g.nz, ny, nx))
+    py = 16
+    while py < 2 * ny - 1:
+        py *= 2
+    if prec == "f64" and py > 2048:
+        with pytest.raises(_native.GravFFTError) as ei:
+            gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+        assert ei.value.status == _native.GF_EUNSUPPORTED
+        return
+    note("sweep %dx%d %s: forward" % (nx, ny, prec))
+    got = run_forward(gf, g, rho, mask=0x7F, prec=prec)
+    st = np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (nx // 3, (2 * ny) // 3), (nx - 1, 0)])
+    want = orc.forward(g, rho, st)
+    scale = np.linalg.norm(want[:, :6])
+    for c in range(7):
+        gv = got[c][st[:, 1], st[:, 0]]
+        # components that vanish on a symmetry line of a thin grid are
+        # compared against the whole tensor's size
+        e = float(np.linalg.norm(gv - want[:, c]) / max(np.linalg.norm(want[:, c]), 1e-3 * scale))
+        assert e <= tol, (NAMES[c], e)
+    # adjoint of a random residual at sampled cells
+    dt = torch.float64 if prec == "f64" else torch.float32
+    r = rng.uniform(-1.0, 1.0, size=(7, ny, nx))
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+    gt = p.adjoint(torch.from_numpy(r).to("cuda", dt)).double().cpu().numpy()
+    torch.cuda.synchronize()
+    p.close()
+    cells = np.array([(0, 0, 0), (nx - 1, ny - 1, g.nz - 1), (nx // 2, ny // 3, 1)])
+    wa = orc.adjoint(g, r, 0x7F, cells)
+    ga = gt[cells[:, 2], cells[:, 1], cells[:, 0]]
+    e = rel(ga, wa)
+    note("sweep %dx%d %s: adjoint rel %.2e" % (nx, ny, prec, e))
+    assert e <= tol
