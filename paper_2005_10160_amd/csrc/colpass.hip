@@ -173,12 +173,57 @@ __device__ __forceinline__ void store_column(cx<T> *dst, const cx<T> (&v)[PPT], 
     }
 }
 
-// Forward column pass.  Per layer n of the split: the density column and the
-// spectrum rows of layer n+1 stream into LDS (asynchronously) while layer n's
-// column is transformed along y and each component accumulates
-// conj(K^_{c,n}) times it; after the last layer one inverse transform per
-// component.  All global reads of the loop are asynchronous copies into LDS.
-template <typename T, int N, int CMAX>
+// One component's term of the layer reduction, slot by slot:
+// acc += K^ x (ADJ) or acc += conj(K^) x (forward), with K^ read from the
+// quarter-plane row kr[ky], ky in [0, N/2].  K^ is k (real component) or i k
+// (IM), and K^(N - ky) = -K^(ky) when the component is odd in y (YO).  A
+// slot's half (ky below or above N/2) is fixed at compile time, so the
+// mirrored index and the sign fold into addresses and operand modifiers;
+// at ky = N/2 an odd component's spectrum is stored as exactly zero.
+template <typename F, typename T, int PPT, int NT, int N, bool IM, bool YO, bool ADJ>
+__device__ __forceinline__ void mac_component(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr, unsigned t)
+{
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const bool upper = F::elem_out(s) >= PPT / 2;
+        const unsigned kq = upper ? (unsigned)(N - NT * F::elem_out(s)) - t : t + NT * F::elem_out(s);
+        T k = kr[kq];
+        if (YO && upper) k = -k;
+        if (IM) {
+            if (ADJ) {  // (i k) x
+                acc[s].re -= k * x[s].im;
+                acc[s].im += k * x[s].re;
+            } else {    // conj(i k) x = -i k x
+                acc[s].re += k * x[s].im;
+                acc[s].im -= k * x[s].re;
+            }
+        } else {
+            acc[s].re += k * x[s].re;
+            acc[s].im += k * x[s].im;
+        }
+    }
+}
+
+template <typename F, typename T, int PPT, int NT, int N, bool ADJ>
+__device__ __forceinline__ void mac_dispatch(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr, unsigned t,
+                                             bool im, bool yo)
+{
+    // im and yo are uniform across the workgroup: a scalar branch
+    if (im) {
+        if (yo) mac_component<F, T, PPT, NT, N, true, true, ADJ>(acc, x, kr, t);
+        else    mac_component<F, T, PPT, NT, N, true, false, ADJ>(acc, x, kr, t);
+    } else {
+        if (yo) mac_component<F, T, PPT, NT, N, false, true, ADJ>(acc, x, kr, t);
+        else    mac_component<F, T, PPT, NT, N, false, false, ADJ>(acc, x, kr, t);
+    }
+}
+
+// Forward column pass.  Per layer n of the split: the density column of layer
+// n+1 streams into registers and its spectrum rows into LDS (asynchronously)
+// while layer n's column is transformed along y and each component
+// accumulates conj(K^_{c,n}) times it; after the last layer one inverse
+// transform per component.
+template <typename T, int N, int CMAX, int KIND>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     __attribute__((amdgpu_waves_per_eu(ColCfg<T, N>::WAVES_PER_EU)))
     col_forward_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec,
@@ -187,6 +232,10 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 {
     using C = ColCfg<T, N>;
     using F = typename C::FFT;
+    // component kinds: compile-time for the common component sets (KIND >= 0:
+    // bit c = imaginary spectrum, bit 8+c = odd in y), else the run-time masks
+    const unsigned im_m = KIND >= 0 ? (unsigned)(KIND & 0xFF) : imag_mask;
+    const unsigned yo_m = KIND >= 0 ? (unsigned)((KIND >> 8) & 0xFF) : yodd_mask;
     constexpr int PPT = C::PPT, NT = C::NT, G = C::G, QP = C::QP;
     constexpr bool AS = C::ASYNC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -251,26 +300,10 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
         }
         F::template run<false>(v, xbuf, xim, t, twp, twlog);
 #pragma unroll
-        for (int c = 0; c < CMAX; ++c) {
-            if (c < Cs) {
-                const bool im = (imag_mask >> c) & 1u;
-                const bool yo = (yodd_mask >> c) & 1u;
-#pragma unroll
-                for (int s = 0; s < PPT; ++s) {
-                    const unsigned ky = t + NT * F::elem_out(s);
-                    const unsigned kq = ky <= N / 2 ? ky : N - ky;
-                    T k = scur[c * QP + kq];
-                    if (yo && ky > N / 2) k = -k;
-                    if (im) {  // the kernel spectrum is i k and enters conjugated: -i k v
-                        acc[c][s].re += k * v[s].im;
-                        acc[c][s].im -= k * v[s].re;
-                    } else {
-                        acc[c][s].re += k * v[s].re;
-                        acc[c][s].im += k * v[s].im;
-                    }
-                }
-            }
-        }
+        for (int c = 0; c < CMAX; ++c)
+            if (c < Cs)
+                mac_dispatch<F, T, PPT, NT, N, false>(acc[c], v, scur + c * QP, t, (im_m >> c) & 1u,
+                                                      (yo_m >> c) & 1u);
         stage_wait<AS>();
     }
 
@@ -289,7 +322,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 // Adjoint column pass: the Cs residual columns are transformed once; per
 // layer the spectrum rows of the next layer stream into LDS while
 // sum_c K^_{c,n} r^_c is formed and inverse-transformed.
-template <typename T, int N, int CMAX>
+template <typename T, int N, int CMAX, int KIND>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     __attribute__((amdgpu_waves_per_eu(ColCfg<T, N>::WAVES_PER_EU)))
     col_adjoint_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec,
@@ -298,6 +331,10 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 {
     using C = ColCfg<T, N>;
     using F = typename C::FFT;
+    // component kinds: compile-time for the common component sets (KIND >= 0:
+    // bit c = imaginary spectrum, bit 8+c = odd in y), else the run-time masks
+    const unsigned im_m = KIND >= 0 ? (unsigned)(KIND & 0xFF) : imag_mask;
+    const unsigned yo_m = KIND >= 0 ? (unsigned)((KIND >> 8) & 0xFF) : yodd_mask;
     constexpr int PPT = C::PPT, NT = C::NT, G = C::G, QP = C::QP;
     constexpr bool AS = C::ASYNC;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -360,26 +397,10 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
         for (int s = 0; s < PPT; ++s) v[s] = cx<T>{T(0), T(0)};
 #pragma unroll
-        for (int c = 0; c < CMAX; ++c) {
-            if (c < Cs) {
-                const bool im = (imag_mask >> c) & 1u;
-                const bool yo = (yodd_mask >> c) & 1u;
-#pragma unroll
-                for (int s = 0; s < PPT; ++s) {
-                    const unsigned ky = t + NT * F::elem_out(s);
-                    const unsigned kq = ky <= N / 2 ? ky : N - ky;
-                    T k = scur[c * QP + kq];
-                    if (yo && ky > N / 2) k = -k;
-                    if (im) {  // (i k) r
-                        v[s].re -= k * rh[c][s].im;
-                        v[s].im += k * rh[c][s].re;
-                    } else {
-                        v[s].re += k * rh[c][s].re;
-                        v[s].im += k * rh[c][s].im;
-                    }
-                }
-            }
-        }
+        for (int c = 0; c < CMAX; ++c)
+            if (c < Cs)
+                mac_dispatch<F, T, PPT, NT, N, true>(v, rh[c], scur + c * QP, t, (im_m >> c) & 1u,
+                                                     (yo_m >> c) & 1u);
         out_to_in<F, T, PPT>(v);
         F::template run<true>(v, xbuf, xim, t, twp, twlog);
         if (w.active)
@@ -394,7 +415,8 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 template <typename TO, int N>
 __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
     col_kgen_kernel(const cx<double> *__restrict__ Rk, TO *__restrict__ spec, int nl, int n0, int Cs,
-                    int nz, int M, unsigned imag_mask, const cx<double> *__restrict__ tw, int twlog)
+                    int nz, int M, unsigned imag_mask, unsigned yodd_mask, const cx<double> *__restrict__ tw,
+                    int twlog)
 {
     using C = ColCfg<double, N>;
     using F = typename C::FFTK;
@@ -431,18 +453,22 @@ __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
     F::template run<false>(v, sre, sim, t, tw, twlog);
     if (active) {
         const bool im = (imag_mask >> c) & 1u;
+        const bool yo = (yodd_mask >> c) & 1u;
         TO *dst = spec + (((size_t)n * U1 + spec_row(uv, M)) * Cs + c) * QPO;
 #pragma unroll
         for (int s = 0; s < PPT; ++s) {
             const unsigned ky = t + NT * F::elem_out(s);
-            if (ky <= N / 2) dst[ky] = (TO)(im ? v[s].im : v[s].re);
+            // a component odd in y has an exactly zero spectrum at ky = Py/2
+            // (its terms at +-b cancel and b = Py/2 is padding); store the
+            // zero rather than the transform's rounding residue
+            if (ky <= N / 2) dst[ky] = (yo && ky == N / 2) ? TO(0) : (TO)(im ? v[s].im : v[s].re);
         }
         // zero the row padding so staged blocks hold no stale values
         if (t < QPO - (N / 2 + 1)) dst[N / 2 + 1 + t] = TO(0);
     }
 }
 
-template <typename T, int N, int CMAX>
+template <typename T, int N, int CMAX, int KIND>
 static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc, int Cs,
                    int nsplit, int lps, unsigned imag_mask, unsigned yodd_mask, const void *tw,
                    int twlog, hipStream_t st)
@@ -452,13 +478,13 @@ static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int 
     const long nblk = (groups + C::G - 1) / C::G;
     const size_t lds = C::lds_bytes(CMAX, true);
     if (lds > lds_limit()) return -3;
-    hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX>), dim3((unsigned)nblk, (unsigned)nsplit),
+    hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
                        dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
                        B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-template <typename T, int N, int CMAX>
+template <typename T, int N, int CMAX, int KIND>
 static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc, int Cs,
                    int nsplit, int lps, unsigned imag_mask, unsigned yodd_mask, const void *tw,
                    int twlog, hipStream_t st)
@@ -468,7 +494,7 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
     const long nblk = (groups + C::G - 1) / C::G;
     const size_t lds = C::lds_bytes(CMAX, false);
     if (lds > lds_limit()) return -3;
-    hipLaunchKernelGGL((col_adjoint_kernel<T, N, CMAX>), dim3((unsigned)nblk, (unsigned)nsplit),
+    hipLaunchKernelGGL((col_adjoint_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
                        dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec,
                        (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask,
                        (const cx<T> *)tw, twlog);
@@ -477,7 +503,7 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
 
 template <typename TO, int N>
 static int run_kgen(const void *Rk, void *spec, int nl, int n0, int Cs, int nz, int M,
-                    unsigned imag_mask, const void *tw, int twlog, hipStream_t st)
+                    unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
     using C = ColCfg<double, N>;
     const long groups = (long)nl * Cs * (M + 1);
@@ -485,21 +511,31 @@ static int run_kgen(const void *Rk, void *spec, int nl, int n0, int Cs, int nz, 
     const size_t lds = (size_t)C::G * 2 * C::FFTK::lds_words() * sizeof(double);
     if (lds > lds_limit()) return -3;
     hipLaunchKernelGGL((col_kgen_kernel<TO, N>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
-                       (const cx<double> *)Rk, (TO *)spec, nl, n0, Cs, nz, M, imag_mask,
+                       (const cx<double> *)Rk, (TO *)spec, nl, n0, Cs, nz, M, imag_mask, yodd_mask,
                        (const cx<double> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 #define GF_COL_SIZES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) X(4096)
 
+// The full tensor set gz, gxx, gxy, gxz, gyy, gyz in slot order: gxz and gyz
+// have imaginary spectra, gxy and gyz are odd in y.
+constexpr unsigned KIND_FULL6_IM = (1u << 3) | (1u << 5);
+constexpr unsigned KIND_FULL6_YO = (1u << 2) | (1u << 5);
+constexpr int KIND_FULL6 = (int)(KIND_FULL6_IM | (KIND_FULL6_YO << 8));
+
 template <typename T, int N>
 static int fwd_c(int Cs, const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc,
                  int nsplit, int lps, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
-    if (Cs <= 1) return run_fwd<T, N, 1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_fwd<T, N, 3>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    return run_fwd<T, N, 6>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs == 6 && im == KIND_FULL6_IM && yo == KIND_FULL6_YO)
+        return run_fwd<T, N, 6, KIND_FULL6>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs == 1 && im == 0 && yo == 0)
+        return run_fwd<T, N, 1, 0>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_fwd<T, N, 1, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_fwd<T, N, 3, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    return run_fwd<T, N, 6, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
 }
 
 template <typename T, int N>
@@ -507,9 +543,13 @@ static int adj_c(int Cs, const void *R, const void *spec, void *Gout, int B, int
                  int nsplit, int lps, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
-    if (Cs <= 1) return run_adj<T, N, 1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_adj<T, N, 3>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    return run_adj<T, N, 6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs == 6 && im == KIND_FULL6_IM && yo == KIND_FULL6_YO)
+        return run_adj<T, N, 6, KIND_FULL6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs == 1 && im == 0 && yo == 0)
+        return run_adj<T, N, 1, 0>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_adj<T, N, 1, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_adj<T, N, 3, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+    return run_adj<T, N, 6, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
 }
 
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
@@ -552,12 +592,14 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
 }
 
 int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,
-                    int nz, int M, unsigned imag_mask, const void *tw, int twlog, hipStream_t st)
+                    int nz, int M, unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog,
+                    hipStream_t st)
 {
 #define CASE(NN)                                                                                  \
     case NN:                                                                                      \
-        return out_fp64 ? run_kgen<double, NN>(Rk, spec, nl, n0, Cs, nz, M, imag_mask, tw, twlog, st) \
-                        : run_kgen<float, NN>(Rk, spec, nl, n0, Cs, nz, M, imag_mask, tw, twlog, st);
+        return out_fp64 ? run_kgen<double, NN>(Rk, spec, nl, n0, Cs, nz, M, imag_mask, yodd_mask, tw, twlog, \
+                                               st)                                                      \
+                        : run_kgen<float, NN>(Rk, spec, nl, n0, Cs, nz, M, imag_mask, yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
     default:
@@ -566,6 +608,8 @@ int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, i
 #undef CASE
 }
 
+// resident workgroups of the forward pass (the generic-kind instance stands
+// for the specialised ones: same LDS, registers within a few)
 template <typename T, int N>
 static int capacity_of(int Cs)
 {
@@ -573,13 +617,13 @@ static int capacity_of(int Cs)
     hipError_t e;
     using C = ColCfg<T, N>;
     if (Cs <= 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 1>, C::THREADS,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 1, -1>, C::THREADS,
                                                          C::lds_bytes(1, true));
     else if (Cs <= 3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 3>, C::THREADS,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 3, -1>, C::THREADS,
                                                          C::lds_bytes(3, true));
     else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 6>, C::THREADS,
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 6, -1>, C::THREADS,
                                                          C::lds_bytes(6, true));
     if (e != hipSuccess || nb < 1) nb = 1;
     int dev = 0, ncu = 0;

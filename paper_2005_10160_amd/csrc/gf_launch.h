@@ -67,7 +67,8 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
 // Plan time: column FFT of the row-transformed kernel fields and extraction
 // of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).
 int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,
-                    int nz, int M, unsigned imag_mask, const void *tw, int twlog, hipStream_t st);
+                    int nz, int M, unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog,
+                    hipStream_t st);
 
 // Plan time: kernel table of layers [n0, n0+nl) for the Cs components in
 // codes[], written into zeroed circulant fields E[nl][Cs][py][px] (double).

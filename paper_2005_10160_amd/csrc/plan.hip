@@ -264,7 +264,7 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
                                p->tw64, p->twlog, st) != 0)
             return fail(GF_EDEVICE, "kernel row transform launch failed");
         if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec, nlc, n0, p->n_spec, p->nz, p->M,
-                                p->imag_mask, p->tw64, p->twlog, st) != 0)
+                                p->imag_mask, p->yodd_mask, p->tw64, p->twlog, st) != 0)
             return fail(GF_EDEVICE, "kernel column transform launch failed");
     }
     return hip_check(hipStreamSynchronize(st), "plan synchronise");
