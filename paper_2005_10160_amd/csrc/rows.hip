@@ -46,9 +46,9 @@ __device__ __forceinline__ Term<T> combo_term(const RowCombo &cmb, int o)
 }
 
 // Forward rows: 16 points a lane for long rows, real and imaginary parts
-// exchanged one after the other through one LDS array per row; rows per
-// workgroup chosen so that the transposed stores are 128-byte segments
-// (16 FP32 or 8 FP64 rows) within 80 KB of LDS and 1024 threads.
+// exchanged one after the other through one LDS array per row.  Rows per
+// workgroup: within 40 KB of LDS and 512 threads, so that two workgroups
+// share a CU and one's loads and stores overlap the other's transforms.
 template <typename T, int M>
 struct RowCfgF {
     static constexpr int PPT = (M >= 1024) ? 16 : ((M >= 8) ? 8 : M);
@@ -56,19 +56,34 @@ struct RowCfgF {
     static constexpr int RADIX = PPT >= 8 ? 8 : PPT;
     using FFT = BlockFFT<T, M, NT, RADIX, true, false, NT == 64>;
     static constexpr int W = FFT::lds_words();
-    // row stride = 4 mod 64 words: the transposed reads (16 rows x 4 units per
-    // wave) then fall in distinct banks
-    static constexpr int WS = W + ((68 - W % 64) % 64);
-    static constexpr int ROW_BYTES = WS * (int)sizeof(T);
+    static constexpr int E = 256 / (int)sizeof(T);   // elements of one 256-byte bank row
     static constexpr int tr_calc()
     {
         int tr = 64;
-        while (tr > 1 && (tr * ROW_BYTES > 80 * 1024 || tr * NT > 1024)) tr /= 2;
+        while (tr > 1 && (tr * (W + E) * (int)sizeof(T) > 40 * 1024 || tr * NT > 512)) tr /= 2;
         return tr;
     }
     static constexpr int TR = tr_calc();
     static constexpr int THREADS = TR * NT;
+    // row stride = E/TR mod E: the transposed reads (TR rows x E/TR units per
+    // bank cycle) then fall in distinct banks
+    static constexpr int SHIFT = E / TR > 0 ? E / TR : 1;
+    static constexpr int WS = W + ((SHIFT - W % E) % E + E) % E;
+    static constexpr int ROW_BYTES = WS * (int)sizeof(T);
+    // register target: waves per SIMD for two resident workgroups
+    static constexpr int WAVES_PER_EU = (2 * THREADS / 256) < 1 ? 1 : ((2 * THREADS / 256) > 8 ? 8 : 2 * THREADS / 256);
 };
+
+// Blocks in XCD-contiguous order: the hardware deals consecutive blocks to
+// the eight XCDs in turn, while neighbouring row groups share the 128-byte
+// lines of the transposed layout; giving each XCD a contiguous range keeps
+// those shared lines in one L2.
+__device__ __forceinline__ unsigned xcd_block()
+{
+    const unsigned nb = gridDim.x, xcd = blockIdx.x % 8u, k = blockIdx.x / 8u;
+    const unsigned q = nb / 8u, rem = nb % 8u;
+    return xcd * q + min(xcd, rem) + k;
+}
 
 // Inverse rows: 8 points a lane, full complex exchange.
 template <typename T, int M>
@@ -100,6 +115,7 @@ struct RowCfg {
 
 template <typename T, int M>
 __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(RowCfgF<T, M>::WAVES_PER_EU)))
     row_r2c_kernel(const T *__restrict__ in, long row_len, int lin, int rows, int ldc, int nsub, int src_per_b,
                    long nrows_total, RowCombo cmb, cx<T> *__restrict__ out,
                    const cx<T> *__restrict__ tw, int twlog)
@@ -112,7 +128,7 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
 
     const unsigned g = threadIdx.x / NT;
     const unsigned t = threadIdx.x % NT;
-    const long gr0 = (long)blockIdx.x * TR;
+    const long gr0 = (long)xcd_block() * TR;
     const long gr = gr0 + g;
     T *sre = lds + (size_t)g * W;
 
@@ -250,13 +266,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T *lds = reinterpret_cast<T *>(smem_raw);
 
-    // Row groups in XCD-contiguous order: the hardware deals consecutive
-    // blocks to the eight XCDs in turn, while neighbouring row groups share
-    // the 128-byte lines of the gather below; giving each XCD a contiguous
-    // range keeps those shared lines in one L2.
-    const unsigned nb = gridDim.x, xcd = blockIdx.x % 8u, k = blockIdx.x / 8u;
-    const unsigned q = nb / 8u, rem = nb % 8u;
-    const long gr0 = (long)(xcd * q + min(xcd, rem) + k) * TR;
+    const long gr0 = (long)xcd_block() * TR;   // XCD-contiguous row groups
 
     // gather X(row)[u] transposed (consecutive lanes read consecutive rows),
     // summing the per-split partials.  Thread item i covers row
