@@ -20,11 +20,18 @@
 
 namespace gf {
 
+// Points per lane and radix of the column transforms.
+template <typename T, int N>
+struct ColShape {
+    static constexpr int PPT = 8;
+    static constexpr int RADIX = 8;
+};
+
 template <typename T, int N>
 struct ColCfg {
-    static constexpr int PPT = 8;
+    static constexpr int PPT = ColShape<T, N>::PPT;
     static constexpr int NT = N / PPT;
-    static constexpr int RADIX = 8;
+    static constexpr int RADIX = ColShape<T, N>::RADIX;
     // the transform of the hot passes: LDS twiddles
     using FFT = BlockFFT<T, N, NT, RADIX, false, true>;
     // the plan-time transform: full exchange, global twiddles
@@ -51,9 +58,9 @@ struct ColCfg {
     static constexpr int THREADS = G * NT;
     static constexpr bool ASYNC = (NT % 64) == 0;                     // groups are whole waves
     static constexpr size_t lds_bytes(int cmax, bool fwd) { return (size_t)G * group_words(cmax, fwd) * sizeof(T); }
-    // register target: FP32 workgroups fit two per CU by LDS, so ask for two
-    // waves per SIMD (at most 256 registers a lane); FP64 ones fit one.
-    static constexpr int WAVES_PER_EU = sizeof(T) == 4 ? (THREADS <= 256 ? 2 : 1) : 1;
+    // register target: waves per SIMD of one workgroup (at least one) times
+    // the workgroups per CU that fit in LDS (two in FP32, one in FP64)
+    static constexpr int WAVES_PER_EU = (THREADS >= 256 ? THREADS / 256 : 1) * (sizeof(T) == 4 ? 2 : 1);
 };
 
 // Row of the resident spectra holding x-bin kx: rows are stored in the order
@@ -409,6 +416,553 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     }
 }
 
+// ---------------------------------------------------------------------------
+// Wave-split column passes (transform lengths N >= 512).
+//
+// One decimation-in-frequency step splits a length-N column transform into
+// NW = N / L independent transforms of length L = 64 * PPT, one per wave:
+//     X[NW k2 + w] = sum_{n2 < L} W_L^{n2 k2} z_w[n2],
+//     z_w[n2] = W_N^{n2 w} sum_{n1 < NW} W_NW^{n1 w} x[n2 + L n1],
+// where only n1 < NW/2 contribute (rows y >= N/2 are the zero padding of the
+// circulant embedding).  Wave w forms z_w from the column (staged in LDS),
+// transforms it with wave-local exchanges (no workgroup barrier) and owns the
+// frequencies ky = NW k2 + w in the layer reduction.  The inverse transform
+// runs the same split backwards: wave w inverse-transforms its frequencies to
+// Y_w[m'], m' < L, and the output is
+//     y[m' + L j] = sum_w W_NW^{-j w} W_N^{-m' w} Y_w[m'],
+// a combination of the waves through LDS once per output column.
+//
+// Resident spectrum rows are stored in residue-block order (spec_pos), so
+// that the frequencies of one wave are contiguous in LDS.
+#ifndef GF_WS_PPT
+#define GF_WS_PPT 4
+#endif
+// Points per lane of the wave transforms for column length N (the same for
+// both precisions, so that one spectrum layout serves both): at most eight
+// waves per column.
+template <int N>
+constexpr int ws_ppt() { return N / (64 * GF_WS_PPT) > 8 ? 8 : GF_WS_PPT; }
+
+// Transform lengths that run in the wave split.
+template <int N>
+constexpr bool use_ws() { return N >= 64 * ws_ppt<N>() && N >= 256; }
+
+// Waves per column of the wave split (1 for lengths that do not use it).
+template <int N>
+constexpr int ws_waves() { return use_ws<N>() ? N / (64 * ws_ppt<N>()) : 1; }
+
+template <typename T, int N>
+struct WsCfg {
+    static constexpr int PPT = ws_ppt<N>();
+    static constexpr int L = 64 * PPT;                                // one wave's transform length
+    static constexpr int NW = N / L;                                  // waves per column
+    static constexpr int G = NW >= 4 ? 1 : 4 / NW;                    // columns per workgroup
+    static constexpr int GT = 64 * NW;                                // threads per column
+    static constexpr int THREADS = G * GT;
+    using FFT = BlockFFT<T, L, 64, (PPT >= 8 ? 8 : PPT), true, true, true>;
+    static constexpr int VEC = 16 / (int)sizeof(T);
+    static constexpr int up(int x) { return ((x + VEC - 1) / VEC) * VEC; }
+    static constexpr int XW = up(FFT::lds_words());                   // one wave's exchange array
+    static constexpr int TWW = up(2 * FFT::stw_entries());            // stage twiddles, shared
+    static constexpr int QP = up(N / 2 + 1);                          // padded spectrum row
+    static constexpr int CW = N;                                      // one column buffer (N/2 complex)
+    // T words per column: two spectrum buffers, two column buffers and the
+    // waves' exchange arrays.  At the end, the first 2N words (re, im of N
+    // values) hold the combination of the waves' inverse transforms.
+    static constexpr int group_words(int cmax) { return 2 * cmax * QP + 2 * CW + NW * XW; }
+    static constexpr size_t lds_bytes(int cmax) { return ((size_t)G * group_words(cmax) + TWW) * sizeof(T); }
+    // register target: waves per SIMD of the workgroups that fit in 160 KB of LDS
+    static constexpr int WG_PER_CU = (int)(163840 / lds_bytes(6)) > 0 ? (int)(163840 / lds_bytes(6)) : 1;
+    static constexpr int WAVES_PER_EU = (THREADS >= 256 ? THREADS / 256 : 1) * WG_PER_CU;
+    static_assert(N % L == 0 && NW >= 1 && NW <= 8, "wave split needs N = NW * L with NW in 1..8");
+};
+
+// Position of frequency ky in [0, N/2] within a resident spectrum row:
+// residue blocks r = ky mod NW (block 0 holds N/(2 NW) + 1 values, the
+// others N/(2 NW)), ky / NW within a block.
+template <int N>
+__host__ __device__ constexpr unsigned spec_pos(unsigned ky)
+{
+    constexpr unsigned NW = (unsigned)ws_waves<N>();
+    if (NW == 1) return ky;
+    const unsigned r = ky % NW, j = ky / NW;
+    return r == 0 ? j : r * (N / NW / 2) + 1u + j;
+}
+
+// exp(-2 pi i k / n) * x for a compile-time k and n in {1, 2, 4, 8}
+template <typename T, int K, int NN>
+__device__ __forceinline__ cx<T> wpow(cx<T> x)
+{
+    constexpr int k8 = ((K % NN + NN) % NN) * (8 / NN);   // in eighths of a turn
+    const T h = T(0.70710678118654752440084436210484903928);
+    if constexpr (k8 == 0) return x;
+    else if constexpr (k8 == 1) return cx<T>{(x.re + x.im) * h, (x.im - x.re) * h};
+    else if constexpr (k8 == 2) return cx<T>{x.im, -x.re};
+    else if constexpr (k8 == 3) return cx<T>{(x.im - x.re) * h, -(x.re + x.im) * h};
+    else if constexpr (k8 == 4) return cx<T>{-x.re, -x.im};
+    else if constexpr (k8 == 5) return cx<T>{-(x.re + x.im) * h, (x.re - x.im) * h};
+    else if constexpr (k8 == 6) return cx<T>{-x.im, x.re};
+    else return cx<T>{(x.re - x.im) * h, (x.re + x.im) * h};
+}
+
+// Stage `nvals` (a multiple of 16 bytes) plus, for an odd number of FP32
+// complex values, the last value through a register: the column copy of a
+// group.  `tail` carries that value until it is written to LDS.
+template <typename T, int GT>
+__device__ __forceinline__ void stage_column(const cx<T> *__restrict__ col, cx<T> *dst, int ny, unsigned tg,
+                                             cx<T> &tail)
+{
+    constexpr int PER = 16 / (int)sizeof(cx<T>);   // complex values per 16 bytes
+    const int nfull = (ny / PER) * PER;
+    stage_rows<T, GT, true>(reinterpret_cast<const T *>(col), reinterpret_cast<T *>(dst), 2u * (unsigned)nfull, tg);
+    if (PER > 1 && nfull < ny && tg == 0) tail = col[ny - 1];
+}
+
+template <typename T>
+__device__ __forceinline__ void put_tail(cx<T> *dst, int ny, unsigned tg, const cx<T> &tail)
+{
+    constexpr int PER = 16 / (int)sizeof(cx<T>);
+    if (PER > 1 && (ny % PER) != 0 && tg == 0) dst[ny - 1] = tail;
+}
+
+// Twiddles of the wave split: W_N^{(lane + 64 e) w} = base * cw[e].
+template <typename T, int N, int PPT>
+struct WsTwiddles {
+    cx<T> base;
+    cx<T> cw[PPT];
+    __device__ __forceinline__ void init(const cx<T> *__restrict__ tw, int twlog, unsigned lane, unsigned w)
+    {
+        constexpr int LOGN = ilog2<N>::value;
+        const unsigned sh = (unsigned)(twlog - LOGN);
+        base = tw[((lane * w) & (N - 1)) << sh];
+#pragma unroll
+        for (int e = 0; e < PPT; ++e) cw[e] = tw[((64u * e * w) & (N - 1)) << sh];
+    }
+    template <bool INV>
+    __device__ __forceinline__ cx<T> apply(cx<T> x, int e) const
+    {
+        const cx<T> t = mul(base, cw[e]);
+        return mul(x, INV ? conjg(t) : t);
+    }
+};
+
+// z_w of the wave split for this lane's slots (FFT input layout), from the
+// column staged in LDS (xc: N/2 values, zero beyond the data; every index
+// read is below N/2: n2 + L n1 < L NW/2 for NW > 1, and with one wave the
+// slots at n2 >= N/2 are the padding).  PART selects the real (1) or
+// imaginary (2) part of a packed column, 0 the whole value.
+template <typename F, typename T, int N, int NW, int L, int PPT, int PART>
+__device__ __forceinline__ void form_z(cx<T> (&v)[PPT], const cx<T> *xc, unsigned lane, unsigned w,
+                                       const cx<T> (&cn)[NW > 1 ? NW / 2 : 1], const WsTwiddles<T, N, PPT> &tws)
+{
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const unsigned n2 = lane + 64u * F::elem_in(s);
+        if (NW == 1 && F::elem_in(s) >= PPT / 2) {   // n2 >= N/2: zero padding, not staged
+            v[s] = cx<T>{T(0), T(0)};
+            continue;
+        }
+        cx<T> a = take_part(xc[n2], PART);
+#pragma unroll
+        for (int n1 = 1; n1 < NW / 2; ++n1) {
+            const cx<T> b = take_part(xc[n2 + (unsigned)L * n1], PART);
+            a = add(a, mul(cn[n1], b));
+        }
+        v[s] = NW > 1 ? tws.template apply<false>(a, F::elem_in(s)) : a;
+    }
+}
+
+// Offsets of wave w's frequencies in a residue-ordered spectrum row: lower
+// slots (ky = NW k2 + w <= N/2) at lo + k2, upper slots (their mirror N - ky)
+// at hi - k2.
+template <int NW, int L>
+__device__ __forceinline__ void ws_offsets(unsigned w, unsigned &lo, unsigned &hi)
+{
+    lo = w == 0 ? 0u : w * (L / 2) + 1u;
+    hi = w == 0 ? (unsigned)L : (NW - w) * (L / 2) + (unsigned)L;
+}
+
+// One component's term of the layer reduction in the wave split (see
+// mac_component for the kinds): slot s of this lane holds k2 = lane + 64 e.
+template <typename F, typename T, int PPT, int NW, bool IM, bool YO, bool ADJ>
+__device__ __forceinline__ void mac_ws(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr, unsigned lane,
+                                       unsigned lo, unsigned hi)
+{
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const bool upper = F::elem_out(s) >= PPT / 2;
+        const unsigned k2 = lane + 64u * F::elem_out(s);
+        T k = upper ? kr[hi - k2] : kr[lo + k2];
+        if (YO && upper) k = -k;
+        if (IM) {
+            if (ADJ) {
+                acc[s].re -= k * x[s].im;
+                acc[s].im += k * x[s].re;
+            } else {
+                acc[s].re += k * x[s].im;
+                acc[s].im -= k * x[s].re;
+            }
+        } else {
+            acc[s].re += k * x[s].re;
+            acc[s].im += k * x[s].im;
+        }
+    }
+}
+
+template <typename F, typename T, int PPT, int NW, bool ADJ>
+__device__ __forceinline__ void mac_ws_dispatch(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr,
+                                                unsigned lane, unsigned lo, unsigned hi, bool im, bool yo)
+{
+    if (im) {
+        if (yo) mac_ws<F, T, PPT, NW, true, true, ADJ>(acc, x, kr, lane, lo, hi);
+        else    mac_ws<F, T, PPT, NW, true, false, ADJ>(acc, x, kr, lane, lo, hi);
+    } else {
+        if (yo) mac_ws<F, T, PPT, NW, false, true, ADJ>(acc, x, kr, lane, lo, hi);
+        else    mac_ws<F, T, PPT, NW, false, false, ADJ>(acc, x, kr, lane, lo, hi);
+    }
+}
+
+// Inverse transform of this wave's frequencies (v in FFT output layout) and
+// its contribution W_N^{-m' w} Y_w[m'] written to the combination arrays
+// (re at cre[w L + m'], im at cre[N + w L + m']).
+template <typename F, typename T, int N, int NW, int L, int PPT>
+__device__ __forceinline__ void ws_inverse_put(cx<T> (&v)[PPT], T *xch, const cx<T> *twp, int twlog, unsigned lane,
+                                               unsigned w, const WsTwiddles<T, N, PPT> &tws, T *cre)
+{
+    out_to_in<F, T, PPT>(v);
+    F::template run<true>(v, xch, nullptr, lane, twp, twlog);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const unsigned m = lane + 64u * F::elem_out(s);
+        const cx<T> a = NW > 1 ? tws.template apply<true>(v[s], F::elem_out(s)) : v[s];
+        cre[w * L + m] = a.re;
+        cre[N + w * L + m] = a.im;
+    }
+}
+
+// Output value m' + L j of the combination (after a barrier), j compile-time.
+template <typename T, int N, int NW, int L, int J, int WI = 0>
+__device__ __forceinline__ cx<T> ws_combine(const T *cre, unsigned mp)
+{
+    if constexpr (WI == NW) {
+        return cx<T>{T(0), T(0)};
+    } else {
+        const cx<T> a{cre[WI * L + mp], cre[N + WI * L + mp]};
+        return add(wpow<T, -J * WI, NW>(a), ws_combine<T, N, NW, L, J, WI + 1>(cre, mp));
+    }
+}
+
+// ws_combine for a block index j in [JJ, NW/2) known only at run time (it is
+// uniform across a wave: blocks of L rows are whole waves of rows).
+template <typename T, int N, int NW, int L, int JJ = 0>
+__device__ __forceinline__ cx<T> ws_combine_j(const T *cre, unsigned mp, unsigned j)
+{
+    if constexpr (JJ + 1 >= NW / 2 || NW == 1) {
+        return ws_combine<T, N, NW, L, JJ>(cre, mp);
+    } else {
+        if (j == (unsigned)JJ) return ws_combine<T, N, NW, L, JJ>(cre, mp);
+        return ws_combine_j<T, N, NW, L, JJ + 1>(cre, mp, j);
+    }
+}
+
+// Outputs y < ny of the combined column: thread tg of the group writes
+// y = tg + GT q, q < (N/2)/GT (consecutive threads, consecutive rows).
+// part: 0 complex column, 1 / 2 the real / imaginary field of a packed
+// column, 3 a real column (array of T).
+template <typename T, int N, int NW, int L, int PPT, int GT, int Q = 0>
+__device__ __forceinline__ void ws_store(const T *cre, cx<T> *dst, unsigned tg, int ny, int part)
+{
+    if constexpr (Q < (N / 2) / GT) {
+        const unsigned y = tg + (unsigned)(GT * Q);
+        if (y < (unsigned)ny) {
+            const unsigned j = y / (unsigned)L;
+            const cx<T> r = ws_combine_j<T, N, NW, L>(cre, y - (unsigned)L * j, j);
+            if (part == 0)
+                dst[y] = r;
+            else if (part == 3)
+                reinterpret_cast<T *>(dst)[y] = r.re;
+            else
+                reinterpret_cast<T *>(dst)[2 * y + (part - 1)] = r.re;
+        }
+        ws_store<T, N, NW, L, PPT, GT, Q + 1>(cre, dst, tg, ny, part);
+    }
+}
+
+// Work of one group in the wave-split passes.  The grid is one-dimensional:
+// blocks [0, nblk_ny) hold the chunks of the real Nyquist unit (kx = Px/2,
+// the imaginary part of packed unit 0), Sny chunks of lps_ny layers per
+// model (nblk_ny = Sny * ceil(B / G)); the other blocks hold the Px/2 main
+// units (uv = 0, the real kx = 0 column, and the complex bins 1 .. Px/2-1)
+// of every model, split by layers into S splits of lps layers (nblk_main
+// blocks per split).  Keeping the odd Nyquist unit out of the main grid lets
+// the main grid fill whole rounds of the device.  All groups of a block run
+// the same layers.
+struct WsItem {
+    unsigned uv, u, b;
+    int part;        // 0: complex column, 1: real part of unit 0, 2: imaginary part of unit 0
+    int n0, n1;      // layers
+    int split;       // split index (main) or chunk index (Nyquist)
+    bool active, nyq;
+};
+
+template <int GT, int G>
+__device__ __forceinline__ WsItem ws_item(unsigned g, int M, int B, int nz, int lps, int nblk_ny, int Sny,
+                                          int lps_ny, int nblk_main)
+{
+    WsItem it;
+    const unsigned bx = blockIdx.x;
+    if ((int)bx < nblk_ny) {
+        // every group of a block takes the same chunk (the layer loop holds
+        // workgroup barriers, so its trip count must be uniform), models
+        // across the groups
+        const unsigned nbb = ((unsigned)B + G - 1) / G;
+        const unsigned bb = (bx % nbb) * G + g;
+        it.active = bb < (unsigned)B;
+        it.b = it.active ? bb : 0u;
+        it.split = (int)(bx / nbb);
+        it.uv = (unsigned)M;
+        it.u = 0;
+        it.part = 2;
+        it.nyq = true;
+        it.n0 = it.split * lps_ny;
+        it.n1 = min(nz, it.n0 + lps_ny);
+    } else {
+        const unsigned bm = bx - (unsigned)nblk_ny;
+        it.split = (int)(bm / (unsigned)nblk_main);
+        const unsigned gi = (bm % (unsigned)nblk_main) * G + g;
+        it.active = gi < (unsigned)M * (unsigned)B;
+        const unsigned gc = it.active ? gi : 0u;
+        it.uv = gc / (unsigned)B;
+        it.b = gc % (unsigned)B;
+        it.u = it.uv;
+        it.part = it.uv == 0 ? 1 : 0;
+        it.nyq = false;
+        it.n0 = it.split * lps;
+        it.n1 = min(nz, it.n0 + lps);
+    }
+    it.uv = __builtin_amdgcn_readfirstlane(it.uv);
+    it.u = __builtin_amdgcn_readfirstlane(it.u);
+    it.b = __builtin_amdgcn_readfirstlane(it.b);
+    it.n0 = __builtin_amdgcn_readfirstlane(it.n0);
+    it.n1 = __builtin_amdgcn_readfirstlane(it.n1);
+    return it;
+}
+
+template <typename T, int N, int CMAX, int KIND>
+__global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(WsCfg<T, N>::WAVES_PER_EU)))
+    col_forward_ws_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec, cx<T> *__restrict__ D,
+                          T *__restrict__ Dny, int B, int nz, int M, int ny, int ldc, int Cs, int lps,
+                          int nblk_ny, int Sny, int lps_ny, int nblk_main, unsigned imag_mask,
+                          unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
+{
+    using C = WsCfg<T, N>;
+    using F = typename C::FFT;
+    constexpr int PPT = C::PPT, L = C::L, NW = C::NW, G = C::G, GT = C::GT, QP = C::QP;
+    const unsigned im_m = KIND >= 0 ? (unsigned)(KIND & 0xFF) : imag_mask;
+    const unsigned yo_m = KIND >= 0 ? (unsigned)((KIND >> 8) & 0xFF) : yodd_mask;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned g = wv / NW, w = wv % NW;
+    const unsigned tg = threadIdx.x - g * GT;
+    T *twq = lds;
+    T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
+    T *sbuf = gb;                                                        // 2 x CMAX x QP
+    cx<T> *cbuf = reinterpret_cast<cx<T> *>(gb + 2 * CMAX * QP);         // 2 x N/2 complex
+    T *xch = gb + 2 * CMAX * QP + 2 * C::CW + w * C::XW;
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
+    F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
+    for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) {
+        cbuf[i] = cx<T>{T(0), T(0)};
+        cbuf[N / 2 + i] = cx<T>{T(0), T(0)};
+    }
+
+    WsTwiddles<T, N, PPT> tws;
+    cx<T> cn[NW > 1 ? NW / 2 : 1];
+    if constexpr (NW > 1) {
+        tws.init(tw, twlog, lane, w);
+        constexpr int LOGN = ilog2<N>::value;
+#pragma unroll
+        for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
+    }
+    unsigned lo, hi;
+    ws_offsets<NW, L>(w, lo, hi);
+
+    const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
+    const unsigned row = spec_row(un.uv, (unsigned)M);
+    const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
+    const int n0 = un.n0;
+    const int n1 = un.n1;
+
+    cx<T> acc[CMAX][PPT];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c)
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) acc[c][s] = cx<T>{T(0), T(0)};
+
+    cx<T> tail{T(0), T(0)};
+    auto stage = [&](int n, int buf) {
+        stage_rows<T, GT, true>(spec + (size_t)n * layer_vals + (size_t)row * Cs * QP, sbuf + buf * CMAX * QP,
+                                (unsigned)Cs * QP, tg);
+        stage_column<T, GT>(column(R, (size_t)un.b * nz + n, M, un.u, ldc), cbuf + buf * (N / 2), ny, tg, tail);
+    };
+    if (n0 < n1) {
+        stage(n0, 0);
+        put_tail(cbuf, ny, tg, tail);
+    }
+    stage_wait<true>();
+
+    for (int n = n0; n < n1; ++n) {
+        const int cur = (n - n0) & 1;
+        if (n + 1 < n1) stage(n + 1, cur ^ 1);
+        cx<T> v[PPT];
+        const cx<T> *xc = cbuf + cur * (N / 2);
+        if (un.part == 0)
+            form_z<F, T, N, NW, L, PPT, 0>(v, xc, lane, w, cn, tws);
+        else if (un.part == 1)
+            form_z<F, T, N, NW, L, PPT, 1>(v, xc, lane, w, cn, tws);
+        else
+            form_z<F, T, N, NW, L, PPT, 2>(v, xc, lane, w, cn, tws);
+        F::template run<false>(v, xch, nullptr, lane, twp, twlog);
+        const T *scur = sbuf + cur * CMAX * QP;
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            if (c < Cs)
+                mac_ws_dispatch<F, T, PPT, NW, false>(acc[c], v, scur + c * QP, lane, lo, hi, (im_m >> c) & 1u,
+                                                      (yo_m >> c) & 1u);
+        if (n + 1 < n1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
+        stage_wait<true>();
+    }
+
+    // every wave is past its last reads of the staged buffers: the first 2N
+    // words of the group's area take the waves' inverse transforms
+    T *cre = gb;
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c) {
+        if (c < Cs) {
+            ws_inverse_put<F, T, N, NW, L, PPT>(acc[c], xch, twp, twlog, lane, w, tws, cre);
+            lds_barrier();
+            if (un.active) {
+                if (un.nyq)   // real partial column of the Nyquist unit
+                    ws_store<T, N, NW, L, PPT, GT>(
+                        cre, reinterpret_cast<cx<T> *>(Dny + (((size_t)un.split * B + un.b) * Cs + c) * (size_t)ldc),
+                        tg, ny, 3);
+                else
+                    ws_store<T, N, NW, L, PPT, GT>(
+                        cre, D + ((((size_t)un.split * B + un.b) * Cs + c) * M + un.u) * (size_t)ldc, tg, ny, un.part);
+            }
+            lds_barrier();
+        }
+    }
+}
+
+// Adjoint in the wave split: the Cs residual columns are staged and
+// transformed once; per layer sum_c K^_{c,n} r^_c is inverse-transformed per
+// wave and combined through LDS.
+template <typename T, int N, int CMAX, int KIND>
+__global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(WsCfg<T, N>::WAVES_PER_EU)))
+    col_adjoint_ws_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec, cx<T> *__restrict__ Gout,
+                          int B, int nz, int M, int ny, int ldc, int Cs, int lps, int nblk_ny, int Sny,
+                          int lps_ny, int nblk_main, unsigned imag_mask, unsigned yodd_mask,
+                          const cx<T> *__restrict__ tw, int twlog)
+{
+    using C = WsCfg<T, N>;
+    using F = typename C::FFT;
+    constexpr int PPT = C::PPT, L = C::L, NW = C::NW, G = C::G, GT = C::GT, QP = C::QP;
+    const unsigned im_m = KIND >= 0 ? (unsigned)(KIND & 0xFF) : imag_mask;
+    const unsigned yo_m = KIND >= 0 ? (unsigned)((KIND >> 8) & 0xFF) : yodd_mask;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned g = wv / NW, w = wv % NW;
+    const unsigned tg = threadIdx.x - g * GT;
+    T *twq = lds;
+    T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
+    T *sbuf = gb;                                                        // 2 x CMAX x QP
+    T *cre = gb + 2 * CMAX * QP;                                         // combination: 2N words
+    cx<T> *rbuf = reinterpret_cast<cx<T> *>(gb);                         // residual columns (setup only)
+    T *xch = gb + 2 * CMAX * QP + 2 * C::CW + w * C::XW;
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
+    F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
+
+    WsTwiddles<T, N, PPT> tws;
+    cx<T> cn[NW > 1 ? NW / 2 : 1];
+    if constexpr (NW > 1) {
+        tws.init(tw, twlog, lane, w);
+        constexpr int LOGN = ilog2<N>::value;
+#pragma unroll
+        for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
+    }
+    unsigned lo, hi;
+    ws_offsets<NW, L>(w, lo, hi);
+
+    const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
+    const unsigned row = spec_row(un.uv, (unsigned)M);
+    const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
+    const int n0 = un.n0;
+    const int n1 = un.n1;
+
+    // residual columns into the spectrum area (Cs x N/2 complex fit in 2 x CMAX x QP words)
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c) {
+        if (c < Cs) {
+            for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) rbuf[c * (N / 2) + i] = cx<T>{T(0), T(0)};
+            cx<T> tail{T(0), T(0)};
+            stage_column<T, GT>(column(R, (size_t)un.b * Cs + c, M, un.u, ldc), rbuf + c * (N / 2), ny, tg, tail);
+            put_tail(rbuf + c * (N / 2), ny, tg, tail);
+        }
+    }
+    stage_wait<true>();
+    cx<T> rh[CMAX][PPT];
+#pragma unroll
+    for (int c = 0; c < CMAX; ++c) {
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) rh[c][s] = cx<T>{T(0), T(0)};
+        if (c < Cs) {
+            const cx<T> *xc = rbuf + c * (N / 2);
+            if (un.part == 0)
+                form_z<F, T, N, NW, L, PPT, 0>(rh[c], xc, lane, w, cn, tws);
+            else if (un.part == 1)
+                form_z<F, T, N, NW, L, PPT, 1>(rh[c], xc, lane, w, cn, tws);
+            else
+                form_z<F, T, N, NW, L, PPT, 2>(rh[c], xc, lane, w, cn, tws);
+            F::template run<false>(rh[c], xch, nullptr, lane, twp, twlog);
+        }
+    }
+    lds_barrier();   // every wave is past its reads of the residual columns
+
+    if (n0 < n1) stage_rows<T, GT, true>(spec + (size_t)n0 * layer_vals + (size_t)row * Cs * QP, sbuf, (unsigned)Cs * QP, tg);
+    stage_wait<true>();
+
+    for (int n = n0; n < n1; ++n) {
+        const int cur = (n - n0) & 1;
+        if (n + 1 < n1)
+            stage_rows<T, GT, true>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
+                                    sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, tg);
+        const T *scur = sbuf + cur * CMAX * QP;
+        cx<T> v[PPT];
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) v[s] = cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int c = 0; c < CMAX; ++c)
+            if (c < Cs)
+                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[c], scur + c * QP, lane, lo, hi, (im_m >> c) & 1u,
+                                                     (yo_m >> c) & 1u);
+        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre);
+        lds_barrier();
+        if (un.active)
+            ws_store<T, N, NW, L, PPT, GT>(cre, Gout + (((size_t)un.b * nz + n) * M + un.u) * (size_t)ldc, tg, ny,
+                                           un.part);
+        stage_wait<true>();
+    }
+}
+
 // Plan time: full-length column FFT of the row-transformed kernel fields
 // (double), keeping one real per frequency of the quarter plane.  Virtual
 // units as in the adjoint.
@@ -461,7 +1015,7 @@ __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
             // a component odd in y has an exactly zero spectrum at ky = Py/2
             // (its terms at +-b cancel and b = Py/2 is padding); store the
             // zero rather than the transform's rounding residue
-            if (ky <= N / 2) dst[ky] = (yo && ky == N / 2) ? TO(0) : (TO)(im ? v[s].im : v[s].re);
+            if (ky <= N / 2) dst[spec_pos<N>(ky)] = (yo && ky == N / 2) ? TO(0) : (TO)(im ? v[s].im : v[s].re);
         }
         // zero the row padding so staged blocks hold no stale values
         if (t < QPO - (N / 2 + 1)) dst[N / 2 + 1 + t] = TO(0);
@@ -470,34 +1024,60 @@ __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
 
 template <typename T, int N, int CMAX, int KIND>
 static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc, int Cs,
-                   int nsplit, int lps, unsigned imag_mask, unsigned yodd_mask, const void *tw,
-                   int twlog, hipStream_t st)
+                   int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
+                   const void *tw, int twlog, hipStream_t st)
 {
-    using C = ColCfg<T, N>;
-    const long groups = (long)(M + 1) * B;
-    const long nblk = (groups + C::G - 1) / C::G;
-    const size_t lds = C::lds_bytes(CMAX, true);
-    if (lds > lds_limit()) return -3;
-    hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
-                       dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
-                       B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+    if constexpr (use_ws<N>()) {
+        using C = WsCfg<T, N>;
+        const long nblk_main = ((long)M * B + C::G - 1) / C::G;
+        const long nblk_ny = (long)nq.Sny * ((B + C::G - 1) / C::G);
+        const size_t lds = C::lds_bytes(CMAX);
+        if (lds > lds_limit()) return -3;
+        if (nq.Sny < 1 || nq.lps_ny < 1 || !nq.Dny) return -2;
+        hipLaunchKernelGGL((col_forward_ws_kernel<T, N, CMAX, KIND>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
+                           dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
+                           (T *)nq.Dny, B, nz, M, ny, ldc, Cs, lps, (int)nblk_ny, nq.Sny, nq.lps_ny,
+                           (int)nblk_main, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+    } else {
+        using C = ColCfg<T, N>;
+        const long groups = (long)(M + 1) * B;
+        const long nblk = (groups + C::G - 1) / C::G;
+        const size_t lds = C::lds_bytes(CMAX, true);
+        if (lds > lds_limit()) return -3;
+        hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
+                           dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
+                           B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T, int N, int CMAX, int KIND>
 static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc, int Cs,
-                   int nsplit, int lps, unsigned imag_mask, unsigned yodd_mask, const void *tw,
-                   int twlog, hipStream_t st)
+                   int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
+                   const void *tw, int twlog, hipStream_t st)
 {
-    using C = ColCfg<T, N>;
-    const long groups = (long)(M + 1) * B;
-    const long nblk = (groups + C::G - 1) / C::G;
-    const size_t lds = C::lds_bytes(CMAX, false);
-    if (lds > lds_limit()) return -3;
-    hipLaunchKernelGGL((col_adjoint_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
-                       dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec,
-                       (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask,
-                       (const cx<T> *)tw, twlog);
+    if constexpr (use_ws<N>()) {
+        using C = WsCfg<T, N>;
+        const long nblk_main = ((long)M * B + C::G - 1) / C::G;
+        const long nblk_ny = (long)nq.Sny * ((B + C::G - 1) / C::G);
+        const size_t lds = C::lds_bytes(CMAX);
+        if (lds > lds_limit()) return -3;
+        if (nq.Sny < 1 || nq.lps_ny < 1) return -2;
+        hipLaunchKernelGGL((col_adjoint_ws_kernel<T, N, CMAX, KIND>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
+                           dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)Gout, B, nz,
+                           M, ny, ldc, Cs, lps, (int)nblk_ny, nq.Sny, nq.lps_ny, (int)nblk_main, imag_mask,
+                           yodd_mask, (const cx<T> *)tw, twlog);
+    } else {
+        using C = ColCfg<T, N>;
+        const long groups = (long)(M + 1) * B;
+        const long nblk = (groups + C::G - 1) / C::G;
+        const size_t lds = C::lds_bytes(CMAX, false);
+        if (lds > lds_limit()) return -3;
+        hipLaunchKernelGGL((col_adjoint_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
+                           dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec,
+                           (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask,
+                           (const cx<T> *)tw, twlog);
+    }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -526,43 +1106,43 @@ constexpr int KIND_FULL6 = (int)(KIND_FULL6_IM | (KIND_FULL6_YO << 8));
 
 template <typename T, int N>
 static int fwd_c(int Cs, const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc,
-                 int nsplit, int lps, unsigned im, unsigned yo, const void *tw, int twlog,
+                 int nsplit, int lps, const NyqSplit &nq, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
     if (Cs == 6 && im == KIND_FULL6_IM && yo == KIND_FULL6_YO)
-        return run_fwd<T, N, 6, KIND_FULL6>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+        return run_fwd<T, N, 6, KIND_FULL6>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
     if (Cs == 1 && im == 0 && yo == 0)
-        return run_fwd<T, N, 1, 0>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 1) return run_fwd<T, N, 1, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_fwd<T, N, 3, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    return run_fwd<T, N, 6, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+        return run_fwd<T, N, 1, 0>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_fwd<T, N, 1, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_fwd<T, N, 3, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+    return run_fwd<T, N, 6, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
 }
 
 template <typename T, int N>
 static int adj_c(int Cs, const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc,
-                 int nsplit, int lps, unsigned im, unsigned yo, const void *tw, int twlog,
+                 int nsplit, int lps, const NyqSplit &nq, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
     if (Cs == 6 && im == KIND_FULL6_IM && yo == KIND_FULL6_YO)
-        return run_adj<T, N, 6, KIND_FULL6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+        return run_adj<T, N, 6, KIND_FULL6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
     if (Cs == 1 && im == 0 && yo == 0)
-        return run_adj<T, N, 1, 0>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 1) return run_adj<T, N, 1, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_adj<T, N, 3, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
-    return run_adj<T, N, 6, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, im, yo, tw, twlog, st);
+        return run_adj<T, N, 1, 0>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_adj<T, N, 1, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_adj<T, N, 3, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+    return run_adj<T, N, 6, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
 }
 
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
-                       int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
     // the kernels skip the upper half of each column (zero padding)
     if (Cs < 1 || Cs > 6 || ny < 1 || 2 * ny > py || ldc < ny) return -2;
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
-        return fp64 ? fwd_c<double, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, imag_mask,    \
+        return fp64 ? fwd_c<double, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,    \
                                         yodd_mask, tw, twlog, st)                                \
-                    : fwd_c<float, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, imag_mask,     \
+                    : fwd_c<float, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,     \
                                        yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
@@ -573,15 +1153,15 @@ int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void 
 }
 
 int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
-                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
+                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
     if (Cs < 1 || Cs > 6 || ny < 1 || 2 * ny > py || ldc < ny) return -2;   // upper half of columns skipped
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
-        return fp64 ? adj_c<double, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, imag_mask, \
+        return fp64 ? adj_c<double, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask, \
                                         yodd_mask, tw, twlog, st)                                \
-                    : adj_c<float, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, imag_mask,  \
+                    : adj_c<float, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,  \
                                        yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
@@ -615,16 +1195,29 @@ static int capacity_of(int Cs)
 {
     int nb = 0;
     hipError_t e;
-    using C = ColCfg<T, N>;
-    if (Cs <= 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 1, -1>, C::THREADS,
-                                                         C::lds_bytes(1, true));
-    else if (Cs <= 3)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 3, -1>, C::THREADS,
-                                                         C::lds_bytes(3, true));
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 6, -1>, C::THREADS,
-                                                         C::lds_bytes(6, true));
+    if constexpr (use_ws<N>()) {
+        using C = WsCfg<T, N>;
+        if (Cs <= 1)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 1, -1>, C::THREADS,
+                                                             C::lds_bytes(1));
+        else if (Cs <= 3)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 3, -1>, C::THREADS,
+                                                             C::lds_bytes(3));
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 6, -1>, C::THREADS,
+                                                             C::lds_bytes(6));
+    } else {
+        using C = ColCfg<T, N>;
+        if (Cs <= 1)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 1, -1>, C::THREADS,
+                                                             C::lds_bytes(1, true));
+        else if (Cs <= 3)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 3, -1>, C::THREADS,
+                                                             C::lds_bytes(3, true));
+        else
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_kernel<T, N, 6, -1>, C::THREADS,
+                                                             C::lds_bytes(6, true));
+    }
     if (e != hipSuccess || nb < 1) nb = 1;
     int dev = 0, ncu = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
@@ -678,9 +1271,13 @@ int spec_row_pitch(bool fp64, int py)
 template <typename T, int N>
 static bool supported_of(int Cs)
 {
-    using C = ColCfg<T, N>;
     const int cmax = Cs <= 1 ? 1 : (Cs <= 3 ? 3 : 6);
-    return C::lds_bytes(cmax, true) <= lds_limit() && C::lds_bytes(cmax, false) <= lds_limit();
+    if constexpr (use_ws<N>()) {
+        return WsCfg<T, N>::lds_bytes(cmax) <= lds_limit();
+    } else {
+        using C = ColCfg<T, N>;
+        return C::lds_bytes(cmax, true) <= lds_limit() && C::lds_bytes(cmax, false) <= lds_limit();
+    }
 }
 
 bool col_supported(bool fp64, int py, int Cs)
@@ -696,11 +1293,46 @@ bool col_supported(bool fp64, int py, int Cs)
 #undef CASE
 }
 
+bool col_nyquist_apart(int py)
+{
+#define CASE(NN) \
+    case NN:     \
+        return use_ws<NN>();
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return false;
+    }
+#undef CASE
+}
+
+int spec_position(int py, int ky)
+{
+#define CASE(NN) \
+    case NN:     \
+        return (int)spec_pos<NN>((unsigned)ky);
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return ky;
+    }
+#undef CASE
+}
+
+template <typename T, int N>
+static constexpr int groups_of()
+{
+    if constexpr (use_ws<N>())
+        return WsCfg<T, N>::G;
+    else
+        return ColCfg<T, N>::G;
+}
+
 int col_forward_groups(bool fp64, int py)
 {
 #define CASE(NN) \
     case NN:     \
-        return fp64 ? ColCfg<double, NN>::G : ColCfg<float, NN>::G;
+        return fp64 ? groups_of<double, NN>() : groups_of<float, NN>();
     switch (py) {
         GF_COL_SIZES(CASE)
     default:

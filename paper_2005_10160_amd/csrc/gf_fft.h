@@ -38,6 +38,17 @@ __device__ __forceinline__ cx<T> rot(cx<T> a)
     return INV ? cx<T>{-a.im, a.re} : cx<T>{a.im, -a.re};
 }
 
+// Workgroup barrier for LDS traffic only: this wave's LDS operations have
+// completed, then all waves meet.  Unlike __syncthreads() (a workgroup fence,
+// which also waits for every outstanding global load, including asynchronous
+// global-to-LDS copies still streaming into another buffer), it leaves global
+// loads in flight.  The memory clobber keeps the compiler from moving memory
+// accesses across it.
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 template <int X>
 struct ilog2 {
     static constexpr int value = 1 + ilog2<X / 2>::value;
@@ -154,7 +165,7 @@ struct BlockFFT {
         if constexpr (WAVESYNC)
             asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         else
-            __syncthreads();
+            lds_barrier();
     }
     static constexpr int PPT = N / NT;
     static constexpr int LOGN = ilog2<N>::value;

@@ -15,6 +15,15 @@ struct RowCombo {
     double w[8][2];
 };
 
+// Layer chunks of the real Nyquist unit (kx = px/2) when the column passes
+// run it apart from the main units (col_nyquist_apart): Sny chunks of lps_ny
+// layers; the forward pass writes its partial columns to
+// Dny[Sny][B][Cs][ldc] (real values), summed by the inverse row pass.
+struct NyqSplit {
+    void *Dny;
+    int Sny, lps_ny;
+};
+
 // Gauss-Legendre rules on [-1,1] of orders 6, 4 and 3 (in that order).
 struct GLRules {
     double x[13];
@@ -40,10 +49,12 @@ int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int
 
 // Inverse row transform: X(b,o,y)[u] = sum_split sum_i w[o][i] D[split][b][src[o][i]][u][y],
 // then real rows of length px, of which the first nx_out are written, times
-// `scale`, to out[b][o][y][x].
+// `scale`, to out[b][o][y][x].  With nq.Sny > 0 the imaginary field of
+// packed unit 0 (the Nyquist bin) is instead sum_chunk sum_i w[o][i]
+// Dny[chunk][b][src[o][i]][y].
 int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nsplit, int nsrc,
-                   int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, void *out, int nx_out,
-                   double scale, const void *tw, int twlog, hipStream_t st);
+                   int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, const NyqSplit &nq,
+                   void *out, int nx_out, double scale, const void *tw, int twlog, hipStream_t st);
 
 // Column data are stored per slab as [unit][y] with M = px/2 units and a
 // leading dimension ldc >= ny (even, so that columns are 16-byte aligned): unit u
@@ -51,18 +62,23 @@ int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nspl
 // kx = 0 (real part) and kx = px/2 (imaginary part).  Spectra are stored
 // [Cs][nz][M+1][py/2+1] (quarter plane, one real per frequency).
 //
+// Whether the column passes of transform length py run the Nyquist unit
+// apart from the px/2 main units (else all px/2 + 1 virtual units share the
+// layer split and the Nyquist results go to the packed unit 0 of D).
+bool col_nyquist_apart(int py);
+
 // Column pass of the forward operator: per column unit u and model b, for
 // each layer n of the split: FFT along y, multiply by conj(K^_{c,n}) and
 // accumulate over n; then inverse FFT per component.
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
-                       int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
-                       unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
+                       int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq,
+                       unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
 // Column pass of the adjoint: FFT of the Cs residual columns, then per layer
 // sum_c K^_{c,n} r^_c and an inverse FFT.
 int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
-                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, unsigned imag_mask,
-                       unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
+                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq,
+                       unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
 // Plan time: column FFT of the row-transformed kernel fields and extraction
 // of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).
@@ -86,6 +102,10 @@ size_t lds_limit();
 
 // Padded length (values) of one resident spectrum row for transform length py.
 int spec_row_pitch(bool fp64, int py);
+
+// Position of frequency ky in [0, py/2] within a resident spectrum row (the
+// wave-split column passes store rows in residue-block order).
+int spec_position(int py, int ky);
 
 // Whether the column passes of transform length py with Cs resident
 // components fit the device's LDS.

@@ -146,10 +146,32 @@ struct gf_plan {
     // Layer split of the forward column pass, and layers per split.  Chosen
     // for one model and used for every batch size, so that a model's result
     // does not depend on the batch it is computed in.
+    // Units of the main column grid: the px/2 main units when the Nyquist
+    // unit runs apart (in layer chunks), else all px/2 + 1.
+    long main_units() const { return gf::col_nyquist_apart(py) ? (long)M : (long)U; }
+    // Layer chunks of the Nyquist unit when it runs apart: up to 32 chunks.
+    void nyq_split(int *Sny, int *lps_ny) const
+    {
+        if (!gf::col_nyquist_apart(py)) {
+            *Sny = 0;
+            *lps_ny = 0;
+            return;
+        }
+        const int target = std::min(nz, 32);
+        const int l = (nz + target - 1) / target;
+        *lps_ny = l;
+        *Sny = (nz + l - 1) / l;
+    }
+    size_t nyq_bytes(int B) const
+    {
+        int Sny, l;
+        nyq_split(&Sny, &l);
+        return elem() * (size_t)Sny * B * n_spec * ldc;
+    }
     void fwd_split(int /*B*/, int *S, int *lps) const
     {
         const int G = gf::col_forward_groups(fp64(), py);
-        const long nblk = ((long)U + G - 1) / G;   // M + 1 uniform units
+        const long nblk = (main_units() + G - 1) / G;
         const int cap = gf::col_forward_capacity(fp64(), py, n_spec, 1);
         // cost in units of one layer of one round of resident workgroups;
         // each split adds a partial-sum write and read (~beta layers)
@@ -173,7 +195,7 @@ struct gf_plan {
     void adj_split(int B, int *S, int *lps) const
     {
         const int G = gf::col_forward_groups(fp64(), py);
-        const long nblk = ((long)U * B + G - 1) / G;  // M + 1 uniform units
+        const long nblk = (main_units() * B + G - 1) / G;
         const int cap = gf::col_forward_capacity(fp64(), py, n_spec, B);
         long s = (2L * cap + nblk - 1) / nblk;
         if (s < 1) s = 1;
@@ -188,7 +210,7 @@ struct gf_plan {
         if (op == GF_OP_FORWARD) {
             int S, l;
             fwd_split(B, &S, &l);
-            return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * n_spec);
+            return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * n_spec) + nyq_bytes(B);
         }
         return celem() * (size_t)M * ldc * ((size_t)B * n_spec + (size_t)B * nz);
     }
@@ -514,6 +536,9 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
     p->fwd_split(batch, &S, &lps);
     char *R = (char *)workspace;
     char *D = R + p->celem() * (size_t)batch * p->nz * p->M * p->ldc;
+    gf::NyqSplit nq{nullptr, 0, 0};
+    p->nyq_split(&nq.Sny, &nq.lps_ny);
+    if (nq.Sny > 0) nq.Dny = D + p->celem() * (size_t)S * batch * p->n_spec * p->M * p->ldc;
     gf::RowCombo ident{};
     ident.identity = 1;
     mark(p, GF_OP_FORWARD, 0, st);
@@ -522,12 +547,12 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 1, st);
     if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec, D, batch, p->nz, p->M, p->ny, p->ldc, p->n_spec, S, lps,
-                               p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
+                               nq, p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 2, st);
     const double scale = kGrav / ((double)p->py * p->M);
     if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->M * p->ldc, S, p->n_spec, p->ny,
-                           p->ldc, p->n_out, batch, p->out_combo, d, p->nx, scale, p->tw, p->twlog, st) != 0)
+                           p->ldc, p->n_out, batch, p->out_combo, nq, d, p->nx, scale, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 3, st);
     return GF_OK;
@@ -543,6 +568,8 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
     hipStream_t st = (hipStream_t)hip_stream;
     int S, lps;
     p->adj_split(batch, &S, &lps);
+    gf::NyqSplit nq{nullptr, 0, 0};
+    p->nyq_split(&nq.Sny, &nq.lps_ny);
     char *R = (char *)workspace;
     char *Gt = R + p->celem() * (size_t)batch * p->n_spec * p->M * p->ldc;
     mark(p, GF_OP_ADJOINT, 0, st);
@@ -551,13 +578,14 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 1, st);
     if (gf::launch_col_adjoint(p->fp64(), p->py, R, p->spec, Gt, batch, p->nz, p->M, p->ny, p->ldc, p->n_spec, S, lps,
-                               p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
+                               nq, p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 2, st);
     gf::RowCombo ident{};
     ident.identity = 1;
     const double scale = kGrav / ((double)p->py * p->M);
-    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, 0, 1, p->nz, p->ny, p->ldc, p->nz, batch, ident, g, p->nx,
+    const gf::NyqSplit none{nullptr, 0, 0};
+    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, 0, 1, p->nz, p->ny, p->ldc, p->nz, batch, ident, none, g, p->nx,
                            scale, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 3, st);
@@ -648,7 +676,8 @@ gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double 
     for (int kx = 0; kx <= p->M; ++kx) {
         const int row = kx == 0 ? 0 : (kx == p->M ? 1 : kx + 1);
         for (int ky = 0; ky < p->Q; ++ky)
-            host_out[(size_t)kx * p->Q + ky] = lay[((size_t)row * p->n_spec + slot) * p->QP + ky];
+            host_out[(size_t)kx * p->Q + ky] =
+                lay[((size_t)row * p->n_spec + slot) * p->QP + gf::spec_position(p->py, ky)];
     }
     return GF_OK;
 }

@@ -257,8 +257,8 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
 template <typename T, int M>
 __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     row_c2r_kernel(const cx<T> *__restrict__ D, long split_stride, int nsplit, int nsrc, int rows, int ldc,
-                   int nsub, long nrows_total, RowCombo cmb, T *__restrict__ out, int nx_out, T sc,
-                   const cx<T> *__restrict__ tw, int twlog)
+                   int nsub, long nrows_total, RowCombo cmb, const T *__restrict__ Dny, int nchunk,
+                   int nbatch, T *__restrict__ out, int nx_out, T sc, const cx<T> *__restrict__ tw, int twlog)
 {
     using C = RowCfg<T, M>;
     using F = typename C::FFT;
@@ -277,7 +277,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
 #pragma unroll
         for (int o = 0; o < 8; ++o) two |= o < nsub && cmb.nterm[o] > 1;
     const unsigned r0 = threadIdx.x % TR, u0 = threadIdx.x / TR;
-    long off0, off1;
+    long off0, off1, noff0, noff1;
     T wa, wb;
     {
         const long grr = gr0 + r0;
@@ -292,6 +292,8 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
         wb = valid ? tm.w1 : T(0);
         off0 = (((long)b * nsrc + tm.s0) * M + u0) * (long)ldc + y;
         off1 = (((long)b * nsrc + tm.s1) * M + u0) * (long)ldc + y;
+        noff0 = ((long)b * nsrc + tm.s0) * (long)ldc + y;
+        noff1 = ((long)b * nsrc + tm.s1) * (long)ldc + y;
     }
     const long ustep = (long)NT * ldc;
     cx<T> acc[PPT];
@@ -312,6 +314,17 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
         }
 #pragma unroll
         for (int i = 0; i < PPT; ++i) acc[i] = add(acc[i], scale(x0[i], wa));
+    }
+    // the Nyquist bin of packed unit 0 (item 0 of the threads with u0 = 0)
+    // from its layer chunks, when the column pass ran it apart
+    if (nchunk > 0 && u0 == 0) {
+        const long cstride = (long)nbatch * nsrc * ldc;
+        T im = T(0);
+        for (int k = 0; k < nchunk; ++k) {
+            im += wa * Dny[k * cstride + noff0];
+            if (two) im += wb * Dny[k * cstride + noff1];
+        }
+        acc[0].im = im;
     }
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
@@ -384,7 +397,7 @@ static int run_r2c(const void *in, long row_len, int lin, int rows, int ldc, int
 
 template <typename T, int M>
 static int run_c2r(const void *D, long split_stride, int nsplit, int nsrc, int rows, int ldc, int nsub,
-                   int nbatch, const RowCombo &cmb, void *out, int nx_out, double scale_,
+                   int nbatch, const RowCombo &cmb, const NyqSplit &nq, void *out, int nx_out, double scale_,
                    const void *tw, int twlog, hipStream_t st)
 {
     using C = RowCfg<T, M>;
@@ -395,7 +408,8 @@ static int run_c2r(const void *D, long split_stride, int nsplit, int nsrc, int r
     if (lds > lds_limit()) return -3;
     hipLaunchKernelGGL((row_c2r_kernel<T, M>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
                        (const cx<T> *)D, split_stride, nsplit, nsrc, rows, ldc, nsub, nrows, cmb,
-                       (T *)out, nx_out, (T)scale_, (const cx<T> *)tw, twlog);
+                       (const T *)nq.Dny, nq.Dny ? nq.Sny : 0, nbatch, (T *)out, nx_out, (T)scale_,
+                       (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -421,16 +435,16 @@ int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int
 }
 
 int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nsplit, int nsrc,
-                   int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, void *out, int nx_out,
-                   double scale_, const void *tw, int twlog, hipStream_t st)
+                   int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, const NyqSplit &nq,
+                   void *out, int nx_out, double scale_, const void *tw, int twlog, hipStream_t st)
 {
     const int M = px / 2;
 #define CASE(MM)                                                                              \
     case MM:                                                                                  \
         return fp64 ? run_c2r<double, MM>(D, split_stride, nsplit, nsrc, rows, ldc, nsub, nbatch, cmb, \
-                                          out, nx_out, scale_, tw, twlog, st)                 \
+                                          nq, out, nx_out, scale_, tw, twlog, st)             \
                     : run_c2r<float, MM>(D, split_stride, nsplit, nsrc, rows, ldc, nsub, nbatch, cmb,  \
-                                         out, nx_out, scale_, tw, twlog, st);
+                                         nq, out, nx_out, scale_, tw, twlog, st);
     switch (M) {
         GF_ROW_SIZES(CASE)
     default:
