@@ -111,6 +111,9 @@ struct RowCfg {
     }
     static constexpr int TR = tr_calc();
     static constexpr int THREADS = TR * NT;
+    // register target: two resident workgroups (512-thread FP64 workgroups
+    // need at most 128 registers a lane); larger workgroups fit one
+    static constexpr int WAVES_PER_EU = THREADS <= 512 ? 2 * THREADS / 256 : 1;
 };
 
 template <typename T, int M>
@@ -256,6 +259,7 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
 
 template <typename T, int M>
 __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(RowCfg<T, M>::WAVES_PER_EU)))
     row_c2r_kernel(const cx<T> *__restrict__ D, long split_stride, int nsplit, int nsrc, int rows, int ldc,
                    int nsub, long nrows_total, RowCombo cmb, const T *__restrict__ Dny, int nchunk,
                    int nbatch, T *__restrict__ out, int nx_out, T sc, const cx<T> *__restrict__ tw, int twlog)
@@ -277,7 +281,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
 #pragma unroll
         for (int o = 0; o < 8; ++o) two |= o < nsub && cmb.nterm[o] > 1;
     const unsigned r0 = threadIdx.x % TR, u0 = threadIdx.x / TR;
-    long off0, off1, noff0, noff1;
+    long off0, off1;
     T wa, wb;
     {
         const long grr = gr0 + r0;
@@ -292,8 +296,6 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
         wb = valid ? tm.w1 : T(0);
         off0 = (((long)b * nsrc + tm.s0) * M + u0) * (long)ldc + y;
         off1 = (((long)b * nsrc + tm.s1) * M + u0) * (long)ldc + y;
-        noff0 = ((long)b * nsrc + tm.s0) * (long)ldc + y;
-        noff1 = ((long)b * nsrc + tm.s1) * (long)ldc + y;
     }
     const long ustep = (long)NT * ldc;
     cx<T> acc[PPT];
@@ -315,17 +317,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
 #pragma unroll
         for (int i = 0; i < PPT; ++i) acc[i] = add(acc[i], scale(x0[i], wa));
     }
-    // the Nyquist bin of packed unit 0 (item 0 of the threads with u0 = 0)
-    // from its layer chunks, when the column pass ran it apart
-    if (nchunk > 0 && u0 == 0) {
-        const long cstride = (long)nbatch * nsrc * ldc;
-        T im = T(0);
-        for (int k = 0; k < nchunk; ++k) {
-            im += wa * Dny[k * cstride + noff0];
-            if (two) im += wb * Dny[k * cstride + noff1];
-        }
-        acc[0].im = im;
-    }
+
 #pragma unroll
     for (int i = 0; i < PPT; ++i) {
         const unsigned r = r0, u = u0 + i * NT;
@@ -341,6 +333,28 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
             qre[idx] = acc[i].re;
             qim[idx] = acc[i].im;
         }
+    }
+    // the Nyquist bin of packed unit 0 (item 0 of the threads with u0 = 0)
+    // from its layer chunks, when the column pass ran it apart
+    if (nchunk > 0 && u0 == 0) {
+        const long cstride = (long)nbatch * nsrc * ldc;
+        // this row's sources in a chunk (recomputed here rather than kept
+        // live through the gather)
+        const long grr = gr0 + r0;
+        const long gc = grr < nrows_total ? grr : 0;
+        const long per_b = (long)nsub * rows;
+        const int b = (int)(gc / per_b);
+        const int o = (int)((gc / rows) % nsub);
+        const int y = (int)(gc % rows);
+        const Term<T> tm = combo_term<T>(cmb, o);
+        const long noff0 = ((long)b * nsrc + tm.s0) * (long)ldc + y;
+        const long noff1 = ((long)b * nsrc + tm.s1) * (long)ldc + y;
+        T im = T(0);
+        for (int k = 0; k < nchunk; ++k) {
+            im += wa * Dny[k * cstride + noff0];
+            if (two) im += wb * Dny[k * cstride + noff1];
+        }
+        lds[(size_t)r0 * C::RWS + F::pad(M)] = im;
     }
     __syncthreads();
 
