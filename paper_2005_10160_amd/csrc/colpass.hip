@@ -434,26 +434,36 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 //
 // Resident spectrum rows are stored in residue-block order (spec_pos), so
 // that the frequencies of one wave are contiguous in LDS.
-#ifndef GF_WS_PPT
-#define GF_WS_PPT 4
+#ifndef GF_WS_PPT64
+#define GF_WS_PPT64 4
 #endif
-// Points per lane of the wave transforms for column length N (the same for
-// both precisions, so that one spectrum layout serves both): at most eight
-// waves per column.
-template <int N>
-constexpr int ws_ppt() { return N / (64 * GF_WS_PPT) > 8 ? 8 : GF_WS_PPT; }
+#ifndef GF_WS_PPT32
+#define GF_WS_PPT32 8
+#endif
+// Points per lane of the wave transforms for column length N: four in FP64
+// (two waves per SIMD fit the accumulators), eight in FP32 (fewer exchanges
+// and column reads through LDS), adjusted so that a column has one to eight
+// waves.  The spectrum layout follows it, so it is fixed per plan precision.
+template <typename T, int N>
+constexpr int ws_ppt()
+{
+    int p = sizeof(T) == 8 ? GF_WS_PPT64 : GF_WS_PPT32;
+    while (p > 1 && 64 * p > N) p /= 2;
+    while (N / (64 * p) > 8) p *= 2;
+    return p;
+}
 
 // Transform lengths that run in the wave split.
 template <int N>
-constexpr bool use_ws() { return N >= 64 * ws_ppt<N>() && N >= 256; }
+constexpr bool use_ws() { return N >= 256; }
 
 // Waves per column of the wave split (1 for lengths that do not use it).
-template <int N>
-constexpr int ws_waves() { return use_ws<N>() ? N / (64 * ws_ppt<N>()) : 1; }
+template <typename T, int N>
+constexpr int ws_waves() { return use_ws<N>() ? N / (64 * ws_ppt<T, N>()) : 1; }
 
 template <typename T, int N>
 struct WsCfg {
-    static constexpr int PPT = ws_ppt<N>();
+    static constexpr int PPT = ws_ppt<T, N>();
     static constexpr int L = 64 * PPT;                                // one wave's transform length
     static constexpr int NW = N / L;                                  // waves per column
     static constexpr int G = NW >= 4 ? 1 : 4 / NW;                    // columns per workgroup
@@ -480,10 +490,10 @@ struct WsCfg {
 // Position of frequency ky in [0, N/2] within a resident spectrum row:
 // residue blocks r = ky mod NW (block 0 holds N/(2 NW) + 1 values, the
 // others N/(2 NW)), ky / NW within a block.
-template <int N>
+template <typename T, int N>
 __host__ __device__ constexpr unsigned spec_pos(unsigned ky)
 {
-    constexpr unsigned NW = (unsigned)ws_waves<N>();
+    constexpr unsigned NW = (unsigned)ws_waves<T, N>();
     if (NW == 1) return ky;
     const unsigned r = ky % NW, j = ky / NW;
     return r == 0 ? j : r * (N / NW / 2) + 1u + j;
@@ -1015,7 +1025,7 @@ __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
             // a component odd in y has an exactly zero spectrum at ky = Py/2
             // (its terms at +-b cancel and b = Py/2 is padding); store the
             // zero rather than the transform's rounding residue
-            if (ky <= N / 2) dst[spec_pos<N>(ky)] = (yo && ky == N / 2) ? TO(0) : (TO)(im ? v[s].im : v[s].re);
+            if (ky <= N / 2) dst[spec_pos<TO, N>(ky)] = (yo && ky == N / 2) ? TO(0) : (TO)(im ? v[s].im : v[s].re);
         }
         // zero the row padding so staged blocks hold no stale values
         if (t < QPO - (N / 2 + 1)) dst[N / 2 + 1 + t] = TO(0);
@@ -1306,11 +1316,11 @@ bool col_nyquist_apart(int py)
 #undef CASE
 }
 
-int spec_position(int py, int ky)
+int spec_position(bool fp64, int py, int ky)
 {
 #define CASE(NN) \
     case NN:     \
-        return (int)spec_pos<NN>((unsigned)ky);
+        return fp64 ? (int)spec_pos<double, NN>((unsigned)ky) : (int)spec_pos<float, NN>((unsigned)ky);
     switch (py) {
         GF_COL_SIZES(CASE)
     default:

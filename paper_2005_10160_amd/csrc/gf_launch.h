@@ -103,9 +103,10 @@ size_t lds_limit();
 // Padded length (values) of one resident spectrum row for transform length py.
 int spec_row_pitch(bool fp64, int py);
 
-// Position of frequency ky in [0, py/2] within a resident spectrum row (the
-// wave-split column passes store rows in residue-block order).
-int spec_position(int py, int ky);
+// Position of frequency ky in [0, py/2] within a resident spectrum row of
+// the given precision (the wave-split column passes store rows in
+// residue-block order).
+int spec_position(bool fp64, int py, int ky);
 
 // Whether the column passes of transform length py with Cs resident
 // components fit the device's LDS.

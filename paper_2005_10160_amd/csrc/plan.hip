@@ -677,7 +677,7 @@ gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double 
         const int row = kx == 0 ? 0 : (kx == p->M ? 1 : kx + 1);
         for (int ky = 0; ky < p->Q; ++ky)
             host_out[(size_t)kx * p->Q + ky] =
-                lay[((size_t)row * p->n_spec + slot) * p->QP + gf::spec_position(p->py, ky)];
+                lay[((size_t)row * p->n_spec + slot) * p->QP + gf::spec_position(p->fp64(), p->py, ky)];
     }
     return GF_OK;
 }
