@@ -51,10 +51,19 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
+def nyquist_chunks(nz):
+    """Layer chunks of the real Nyquist column unit (the column pass runs it
+    apart from the main units): up to 32 chunks."""
+    target = min(nz, 32)
+    lps = (nz + target - 1) // target
+    return (nz + lps - 1) // lps
+
+
 def colpass_algorithmic_bytes(p, B):
     """Bytes the forward column pass must move per launch: every resident
     spectrum value once, the row-transformed density columns once, and the
-    per-split partial data spectra once (quarter-plane spectra, one real per
+    partial data columns once (per layer split for the main units, per layer
+    chunk for the real Nyquist unit; quarter-plane spectra, one real per
     frequency; complex intermediates)."""
     info = p.info
     s = 8 if p.precision == "f64" else 4
@@ -63,9 +72,10 @@ def colpass_algorithmic_bytes(p, B):
     spectra = info.n_spec * info.nz * (M + 1) * Q * s
     R = B * info.nz * M * info.ny * 2 * s
     ws = p.workspace_bytes("forward", B)
-    S = round((ws // (2 * s * M * info.ny) - B * info.nz) / (B * info.n_spec))
+    S = int((ws // (2 * s * M * info.ny) - B * info.nz) // (B * info.n_spec))
     D = S * B * info.n_spec * M * info.ny * 2 * s
-    return spectra + R + D, S
+    Dny = nyquist_chunks(info.nz) * B * info.n_spec * info.ny * s
+    return spectra + R + D + Dny, S
 
 
 def time_forward(p, rho, d, ws, steps, warmup):
@@ -217,7 +227,7 @@ def main():
             traffic = None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": "col_forward_kernel (FFT along y + layer reduction + inverse FFT)",
+                "kernel": "col_forward_ws_kernel (FFT along y + layer reduction + inverse FFT)",
                 "algorithmic_bytes_per_launch": alg_bytes, "layer_splits": S,
                 "kernel_ms": round(col_ms, 4)}
     line = {
