@@ -13,7 +13,9 @@ the number of kernel-matrix entries the operator applies per second
 
 One JSON line is printed.  Besides the headline FP64 forward it carries the
 FP32 path, the adjoint, a live roofline of the dominant kernel (the column
-pass), the CPU oracle timed on a bounded sample, and a served-latency run:
+pass), the batched inversion-step workload (512^2 x 128, 32 models, forward
+and adjoint in both precisions), the CPU oracle timed on a bounded sample,
+and a served-latency run:
 a seeded Poisson trace of mixed requests (3 s at 200 req/s by default)
 replayed through the FP32 continuous-batching server and through the plain
 FP64 operator (FIFO, one model per call), each with p50/p99 latency.
@@ -22,6 +24,7 @@ FP64 operator (FIFO, one model per call), each with p50/p99 latency.
 import argparse
 import hashlib
 import json
+import math
 import os
 import statistics
 import sys
@@ -113,6 +116,81 @@ def time_passes(p, rho, d, ws, steps, op="forward"):
     return np.array(out)
 
 
+def batched_step(steps, warmup):
+    """Inversion-step workload: 512 x 512 x 128, 20 m cells, h = 10 m, all six
+    components, 32 density models sharing the geometry (uniform(-0.5, 0.5)
+    g/cm^3 plus a 4x4x3 +1.0 g/cm^3 block per model, drawn on the device from
+    a seeded generator).  One batched forward and one batched adjoint per
+    precision, median of `steps` applies after `warmup`."""
+    import torch
+    import paper_2005_10160_amd as gf
+    from synth import PRESETS
+    g = PRESETS["inversion"]
+    B = 32
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(400)
+    out = {"workload": "inversion step, %dx%dx%d, %g m cells, h=%g m, 6 components, batch %d"
+                       % (g.nx, g.ny, g.nz, g.dx, g.h, B)}
+    evals = float(B) * 6 * g.nd * g.nm
+    for prec in ("f32", "f64"):
+        dt = torch.float64 if prec == "f64" else torch.float32
+        s = 8 if prec == "f64" else 4
+        log("bench: batched %s" % prec)
+        p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, gf.ALL6, prec, device=dev)
+        rho = (torch.rand((B, g.nz, g.ny, g.nx), generator=gen, device=dev, dtype=dt) - 0.5) * 1000.0
+        for b in range(B):
+            l0, m0, n0 = (int(v) for v in torch.randint(0, g.nx - 4, (3,), generator=gen, device=dev).tolist())
+            n0 = 1 + n0 % (g.nz - 4)
+            rho[b, n0:n0 + 3, m0:m0 + 4, l0:l0 + 4] += 1000.0
+        d = torch.empty((B, 6, g.ny, g.nx), dtype=dt, device=dev)
+        gout = torch.empty_like(rho)
+        wsb = max(p.workspace_bytes("forward", B), p.workspace_bytes("adjoint", B))
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        res = {}
+        for op in ("forward", "adjoint"):
+            run = (lambda: p.forward(rho, d, ws)) if op == "forward" else (lambda: p.adjoint(d, gout, ws))
+            for _ in range(warmup):
+                run()
+            torch.cuda.synchronize()
+            times = []
+            for _ in range(steps):
+                a = torch.cuda.Event(enable_timing=True)
+                e = torch.cuda.Event(enable_timing=True)
+                a.record()
+                run()
+                e.record()
+                torch.cuda.synchronize()
+                times.append(a.elapsed_time(e))
+            ms = statistics.median(times)
+            # transform and reduction flop at 5 N log2 N per complex transform
+            # of N points: the row transforms (a real row of Px values as a
+            # complex one of Px/2), one column transform per layer and unit,
+            # 4 flop per frequency, layer and component for the reduction,
+            # and the inverse transforms per component
+            info = p.info
+            U = info.px // 2 + 1
+            lg = lambda n: math.log2(n)
+            rowf = 5 * (info.px // 2) * lg(info.px // 2)
+            colf = 5 * info.py * lg(info.py)
+            flop = B * (g.nz * g.ny * rowf + g.nz * U * colf + 4 * 6 * g.nz * U * info.py
+                        + 6 * U * colf + 6 * g.ny * rowf)
+            peak_tf = 78.6 if prec == "f64" else 157.3
+            # compulsory bytes: resident spectra once, every model's density
+            # (or residual) and data once
+            spectra = p.spectra_bytes
+            io = B * s * (g.nz * g.nx * g.ny + 6 * g.nx * g.ny)
+            res[op] = {"ms": round(ms, 3), "effective_evals_per_s": evals / (ms * 1e-3),
+                       "compulsory_GBs": round((spectra + io) / (ms * 1e-3) / 1e9, 1),
+                       "compulsory_frac_of_8TBs": round((spectra + io) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 3),
+                       "fft_TFLOPs": round(flop / (ms * 1e-3) / 1e12, 2),
+                       "fft_frac_of_vector_peak": round(flop / (ms * 1e-3) / 1e12 / peak_tf, 3)}
+        out[prec] = res
+        p.close()
+        del rho, d, gout, ws
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(g, rho_np, n_stations, threads):
     import oracle
     if threads:
@@ -144,6 +222,7 @@ def main():
     ap.add_argument("--cpu-stations", type=int, default=2)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 32-model inversion-step timing")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the replayed request trace (0: no serving run)")
     ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
@@ -269,6 +348,9 @@ def main():
                        "colpass_GBs": round(a32 / (c32 * 1e-3) / 1e9, 1), "plan_ms": round(r32["plan_ms"], 1)}
         r32["plan"].close()
         del r32
+
+    if not args.no_batched and not args.small:
+        line["batched"] = batched_step(5, 1)
 
     if args.serve_seconds > 0:
         from paper_2005_10160_amd import serve
