@@ -169,6 +169,41 @@ def test_batch_equals_single(gf):
     p.close()
 
 
+# column lengths 256, 512 and 1024: several column units per workgroup and
+# one to four waves per column in the wave split; 3 models (not a multiple of
+# the columns per workgroup) and 37 layers (Nyquist chunks of 2 layers, the
+# last one short)
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+@pytest.mark.parametrize("nx,ny", [(100, 120), (70, 200), (60, 300)])
+def test_wave_split_batches(gf, orc, nx, ny, prec, tol):
+    g = Geometry(nx, ny, 37, 20.0, 25.0, 15.0, 7.0)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (4, 5, 6)])
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+    note("wave split %dx%dx%d %s: batch of 3" % (nx, ny, g.nz, prec))
+    both = p.forward(torch.from_numpy(rho).to("cuda", dt)).double().cpu().numpy()
+    for b in range(3):
+        one = p.forward(torch.from_numpy(rho[b]).to("cuda", dt)).double().cpu().numpy()
+        assert np.array_equal(both[b], one), b
+    st = np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (nx // 3, (2 * ny) // 3)])
+    want = orc.forward(g, rho[1], st)
+    for c in range(7):
+        gv = both[1][c][st[:, 1], st[:, 0]]
+        e = rel(gv, want[:, c])
+        assert e <= tol, (NAMES[c], e)
+    rng = np.random.default_rng(nx + ny)
+    r = rng.uniform(-1.0, 1.0, size=(3, 7, ny, nx))
+    gt = p.adjoint(torch.from_numpy(r).to("cuda", dt)).double().cpu().numpy()
+    for b in range(3):
+        one = p.adjoint(torch.from_numpy(r[b]).to("cuda", dt)).double().cpu().numpy()
+        assert np.array_equal(gt[b], one), b
+    lhs = float(np.sum(both * r))
+    rhs = float(np.sum(rho * gt))
+    dtol = 1e-13 if prec == "f64" else 1e-6
+    assert abs(lhs - rhs) <= dtol * np.linalg.norm(both) * np.linalg.norm(r), (lhs, rhs)
+    p.close()
+
+
 def test_deterministic(gf):
     g = Geometry(40, 30, 12, 20.0, 20.0, 20.0, 10.0)
     rho = tiny_density(g.nx, g.ny, g.nz, seed=9, block=None)
