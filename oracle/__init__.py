@@ -9,7 +9,7 @@ The arithmetic lives in ``gravity_oracle.c`` (plain C, x87 long double,
 OpenMP over stations / layers, no FMA contraction); this module only marshals
 numpy arrays through ctypes.
 
-Component order everywhere: gz, gxx, gxy, gxz, gyy, gyz, gzz.
+Component order everywhere: gz, gxx, gxy, gxz, gyy, gyz, gzz, gx, gy.
 """
 
 import ctypes
@@ -19,8 +19,8 @@ import threading
 
 import numpy as np
 
-COMPONENTS = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz")
-NCOMP = 7
+COMPONENTS = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz", "gx", "gy")
+NCOMP = 9
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gravity_oracle.c")
@@ -100,7 +100,7 @@ def set_threads(n):
 
 def prism(x1, x2, y1, y2, z1, z2):
     """Kernel of one prism with bounds relative to the station (source minus
-    station, z down, 0 < z1 < z2), per kg/m^3, in SI: array of 7."""
+    station, z down, 0 < z1 < z2), per kg/m^3, in SI: array of NCOMP."""
     out = np.zeros(NCOMP)
     _load().orc_prism(float(x1), float(x2), float(y1), float(y2), float(z1), float(z2), _pd(out))
     return out
@@ -128,7 +128,7 @@ def offset_kernels(geom, n, a, b, mode=0):
     """Kernel of the cell at offset (a, b) = (l-p, m-q) in layer n relative to
     its station (translation equivalence, eq. 7/10).  mode 0: closed form;
     mode 1: closed form near, 8^3 Gauss-Legendre beyond 24 half-diagonals.
-    Returns (len(a), 7)."""
+    Returns (len(a), NCOMP)."""
     a = np.ascontiguousarray(a, dtype=np.int32).ravel()
     b = np.ascontiguousarray(b, dtype=np.int32).ravel()
     assert a.shape == b.shape
@@ -141,7 +141,7 @@ def offset_kernels(geom, n, a, b, mode=0):
 
 
 def kernel_table(geom, n, mode=0):
-    """Full offset table of layer n: (7, 2ny-1, 2nx-1), index [c][b+ny-1][a+nx-1]."""
+    """Full offset table of layer n: (NCOMP, 2ny-1, 2nx-1), index [c][b+ny-1][a+nx-1]."""
     aa, bb = np.meshgrid(np.arange(-(geom.nx - 1), geom.nx), np.arange(-(geom.ny - 1), geom.ny))
     k = offset_kernels(geom, n, aa.ravel(), bb.ravel(), mode)
     return k.T.reshape(NCOMP, 2 * geom.ny - 1, 2 * geom.nx - 1)
@@ -150,7 +150,7 @@ def kernel_table(geom, n, mode=0):
 def forward(geom, rho, stations=None):
     """Direct sum d = G rho (eq. 3) at stations (array of (p, q)); all
     stations in row order (q major) when None.  rho: (nz,ny,nx) or
-    (nb,nz,ny,nx) in kg/m^3.  Returns (nb, nst, 7) (nb dropped for 3-D rho)."""
+    (nb,nz,ny,nx) in kg/m^3.  Returns (nb, nst, NCOMP) (nb dropped for 3-D rho)."""
     rho = np.asarray(rho, dtype=np.float64)
     squeeze = rho.ndim == 3
     if squeeze:
@@ -172,7 +172,7 @@ def forward(geom, rho, stations=None):
 
 
 def forward_grid(geom, rho):
-    """Direct sum at every station: (nb, 7, ny, nx) (nb dropped for 3-D rho)."""
+    """Direct sum at every station: (nb, NCOMP, ny, nx) (nb dropped for 3-D rho)."""
     squeeze = np.asarray(rho).ndim == 3
     out = forward(geom, rho)
     if squeeze:
@@ -184,7 +184,7 @@ def forward_grid(geom, rho):
 
 def adjoint(geom, r, mask, cells=None):
     """Direct adjoint g(l,m,n) = sum_c sum_{p,q} G_c[(p,q),(l,m,n)] r_c(p,q).
-    r: (7, ny, nx) or (nb, 7, ny, nx) indexed by component slot; only slots in
+    r: (NCOMP, ny, nx) or (nb, NCOMP, ny, nx) indexed by component slot; only slots in
     ``mask`` (bit c = component c) are read.  cells: array of (l, m, n);
     every cell when None (returned as (nb, nz, ny, nx))."""
     r = np.asarray(r, dtype=np.float64)
@@ -222,7 +222,7 @@ def dense_matrix(geom, comp):
 
 def blocks_at_stations(geom, blocks, stations):
     """Superposition of uniform blocks, each integrated as one merged prism.
-    blocks: iterable of (l0, l1, m0, m1, n0, n1, rho).  Returns (nst, 7)."""
+    blocks: iterable of (l0, l1, m0, m1, n0, n1, rho).  Returns (nst, NCOMP)."""
     blocks = list(blocks)
     blk = np.ascontiguousarray(np.array([b[:6] for b in blocks], dtype=np.int32).reshape(-1))
     val = np.ascontiguousarray(np.array([b[6] for b in blocks], dtype=np.float64))

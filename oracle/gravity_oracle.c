@@ -25,7 +25,7 @@
  *   - Relative coordinates are source minus station, so z > 0 inside cells.
  *   - U = G rho \iiint dV / r;  g = grad U (pointing at the mass, gz > 0 for
  *     a positive mass below);  T_ab = d^2 U / da db.
- *   - Component order: gz, gxx, gxy, gxz, gyy, gyz, gzz.
+ *   - Component order: gz, gxx, gxy, gxz, gyy, gyz, gzz, gx, gy.
  *   - G = 6.672e-11 N m^2 / kg^2, the constant printed with eq. 2.
  *
  * Closed forms, with corners (x_i, y_j, z_k), i,j,k in {lower, upper}, and
@@ -40,10 +40,20 @@
  *   gxy =  G rho sum mu ln(z + r)
  *   gxz =  G rho sum mu asinh(y / sqrt(x^2+z^2))
  *   gyz =  G rho sum mu asinh(x / sqrt(y^2+z^2))
+ *   gx  = -G rho sum mu [ z asinh(y/sqrt(x^2+z^2)) + y asinh(z/sqrt(x^2+y^2))
+ *                         - x atan(y z / (x r)) ]
+ *   gy  = -G rho sum mu [ x asinh(z/sqrt(x^2+y^2)) + z asinh(x/sqrt(y^2+z^2))
+ *                         - y atan(x z / (y r)) ]
  * The tensor forms follow from integrating (3 a b - r^2 delta_ab) / r^5 one
  * axis at a time; eq. 2 reads ln(y/sqrt(x^2+z^2) + sqrt(1 + y^2/(x^2+z^2))),
  * which is asinh(y/sqrt(x^2+z^2)) and is evaluated as such (the form
- * ln(y + r) cancels catastrophically for y < 0).
+ * ln(y + r) cancels catastrophically for y < 0).  The first derivatives gx
+ * and gy (whose kernels section 2.2.3 also states to be BTTB) integrate x/r^3
+ * and y/r^3: the triple integral is symmetric in its three variables, so
+ * their corner terms are the gz term with x and z (for gx) or y and z (for
+ * gy) exchanged.  Corners never lie on x = 0 or y = 0 (cell faces sit at
+ * half-integer offsets), and the jump of atan(y z / (x r)) across x = 0 is
+ * killed by its factor x.
  */
 #include <math.h>
 #include <stdlib.h>
@@ -54,7 +64,8 @@
 
 typedef long double ld;
 
-enum { C_GZ = 0, C_GXX = 1, C_GXY = 2, C_GXZ = 3, C_GYY = 4, C_GYZ = 5, C_GZZ = 6, NCOMP = 7 };
+enum { C_GZ = 0, C_GXX = 1, C_GXY = 2, C_GXZ = 3, C_GYY = 4, C_GYZ = 5, C_GZZ = 6, C_GX = 7, C_GY = 8,
+       NCOMP = 9 };
 
 static const ld GRAV = 6.672e-11L; /* eq. 2 */
 
@@ -82,6 +93,12 @@ void orc_set_threads(int n)
 /* ------------------------------------------------------------------------ */
 /* Corner terms of the closed forms (without G rho and without mu).          */
 /* ------------------------------------------------------------------------ */
+
+/* a * v where v grows at most like ln(1/|a|) or stays bounded as a -> 0:
+ * the product's limit at a = 0 is 0 (corners on the axes of a box that the
+ * station touches). */
+static ld times(ld a, ld v) { return a == 0 ? 0 : a * v; }
+
 static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
 {
     ld x2 = x * x, y2 = y * y, z2 = z * z;
@@ -90,6 +107,8 @@ static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
     ld syz = sqrtl(y2 + z2);
     ld ash_y = asinhl(y / sxz);        /* = ln(y + r) - ln sqrt(x^2+z^2) */
     ld ash_x = asinhl(x / syz);        /* = ln(x + r) - ln sqrt(y^2+z^2) */
+    ld sxy = sqrtl(x2 + y2);
+    ld ash_z = sxy > 0 ? asinhl(z / sxy) : 0;   /* only ever multiplied by x or y */
     ld at_z = atanl((x * y) / (z * r));
     f[C_GZ] = -(x * ash_y + y * ash_x - z * at_z);
     f[C_GXX] = -atan2l(y * z, x * r);
@@ -98,6 +117,8 @@ static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
     f[C_GXY] = logl(z + r);
     f[C_GXZ] = ash_y;
     f[C_GYZ] = ash_x;
+    f[C_GX] = -(z * ash_y + times(y, ash_z) - times(x, x != 0 ? atanl((y * z) / (x * r)) : 0));
+    f[C_GY] = -(times(x, ash_z) + z * ash_x - times(y, y != 0 ? atanl((x * z) / (y * r)) : 0));
 }
 
 /* mu for corner (i,j,k), each 0 = lower bound, 1 = upper bound. */
@@ -120,7 +141,7 @@ static void prism_ld(ld x1, ld x2, ld y1, ld y2, ld z1, ld z2, ld out[NCOMP])
 }
 
 /* Public: one prism given by its bounds relative to the station
- * (source minus station, z down, z1 < z2, z1 > 0).  out[7] in SI per kg/m^3. */
+ * (source minus station, z down, z1 < z2, z1 > 0).  out[9] in SI per kg/m^3. */
 void orc_prism(double x1, double x2, double y1, double y2, double z1, double z2, double out[NCOMP])
 {
     ld o[NCOMP];
@@ -168,7 +189,7 @@ static void gl_rule(int n, ld *x, ld *w)
 }
 
 /* Point-source kernel at relative position (x,y,z) of a unit mass, G included:
- * gz = G z / r^3, T_ab = G (3 a b - r^2 delta_ab) / r^5. */
+ * g_a = G a / r^3, T_ab = G (3 a b - r^2 delta_ab) / r^5. */
 static void point_kernel(ld x, ld y, ld z, ld k[NCOMP])
 {
     ld r2 = x * x + y * y + z * z;
@@ -182,6 +203,8 @@ static void point_kernel(ld x, ld y, ld z, ld k[NCOMP])
     k[C_GXY] = GRAV * 3 * x * y * ir5;
     k[C_GXZ] = GRAV * 3 * x * z * ir5;
     k[C_GYZ] = GRAV * 3 * y * z * ir5;
+    k[C_GX] = GRAV * x * ir3;
+    k[C_GY] = GRAV * y * ir3;
 }
 
 #define GL_MAX 32
@@ -273,7 +296,7 @@ static void cell_bounds(int a, int b, int n, double dx, double dy, double dz, do
  *         half-diagonals, otherwise one 8^3 Gauss-Legendre rule over the cell
  *         (at that distance its truncation error is far below long-double
  *         rounding, while the closed form starts to lose digits).
- * out[count][7]. */
+ * out[count][9]. */
 int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int count, const int *a,
                        const int *b, int mode, double *out)
 {
@@ -303,7 +326,7 @@ int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int cou
 /* that share them (each cell still sums its own eight corners).             */
 /* ------------------------------------------------------------------------ */
 
-/* Fill plane[(jy*(nxn) + ix)*7 + c] with corner_terms at x = (v0 + ix - 1/2) dx,
+/* Fill plane[(jy*(nxn) + ix)*NCOMP + c] with corner_terms at x = (v0 + ix - 1/2) dx,
  * y = (w0 + jy - 1/2) dy, depth z. */
 static void fill_plane(ld *plane, int v0, int nxn, int w0, int nyn, double dx, double dy, ld z)
 {
@@ -337,7 +360,7 @@ static inline void cell_from_planes(const ld *lo, const ld *hi, int nxn, int ix,
 /* Direct forward sum (eq. 3) at chosen stations.                            */
 /* ------------------------------------------------------------------------ */
 
-/* rho[nb][nz][ny][nx] (kg/m^3).  Stations (sp[s], sq[s]).  out[nb][nst][7].
+/* rho[nb][nz][ny][nx] (kg/m^3).  Stations (sp[s], sq[s]).  out[nb][nst][NCOMP].
  * Work is split over (station, chunk of consecutive layers), so each node
  * plane is evaluated once per chunk; partial sums are kept per layer and
  * reduced in layer order, so the result does not depend on the thread count
@@ -417,7 +440,7 @@ int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double 
 /* Direct adjoint sum: g(l,m,n) = sum_c sum_{p,q} G_c[(p,q),(l,m,n)] r_c(p,q) */
 /* ------------------------------------------------------------------------ */
 
-/* r[nb][7][ny][nx] indexed by component slot (unused slots may hold anything,
+/* r[nb][NCOMP][ny][nx] indexed by component slot (unused slots may hold anything,
  * only comps in mask are read).  Cells (cl, cm, cn).  out[nb][ncell]. */
 int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
                 unsigned mask, const double *r, int ncell, const int *cl, const int *cm,
@@ -501,7 +524,7 @@ int orc_dense_matrix(int nx, int ny, int nz, double dx, double dy, double dz, do
 /* Blocks k: cells l in [blk[6k],blk[6k+1]), m in [blk[6k+2],blk[6k+3]),
  * n in [blk[6k+4],blk[6k+5]) with density val[k].  Since the closed form
  * integrates any box, a block needs one evaluation per station instead of one
- * per cell.  out[nst][7] = sum_k val[k] * K(block k). */
+ * per cell.  out[nst][NCOMP] = sum_k val[k] * K(block k). */
 int orc_blocks_at_stations(int nx, int ny, int nz, double dx, double dy, double dz, double h,
                            int nblk, const int *blk, const double *val, int nst, const int *sp,
                            const int *sq, double *out)

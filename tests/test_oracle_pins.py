@@ -5,7 +5,7 @@ retyped copy of its own formulas:
   * Gauss-Legendre brute force of the point kernel (independent integration);
   * the point-mass far-field limit and its convergence order;
   * the trace-free identity (eq. 1 discussion) and tensor symmetry;
-  * finite differences of gz in the station position;
+  * finite differences of gz, gx and gy in the station position;
   * superposition of cells against one merged prism, and the Bouguer slab;
   * the dense-matrix structure claims (eq. 7, eq. 15-17, BTTB);
   * numpy's FFT applied to the oracle's kernel table (eq. 18);
@@ -18,7 +18,8 @@ import pytest
 
 from synth import Geometry, tiny_density, paper_e1_geometry, paper_e1_density
 
-GZ, GXX, GXY, GXZ, GYY, GYZ, GZZ = range(7)
+GZ, GXX, GXY, GXZ, GYY, GYZ, GZZ, GX, GY = range(9)
+TENSOR = [GXX, GXY, GXZ, GYY, GYZ, GZZ]
 
 
 def rel(a, b):
@@ -63,14 +64,16 @@ def cancellation_factor(box):
 
 def test_closed_form_matches_gauss_legendre(orc):
     """Every component, sign and corner convention against brute-force
-    quadrature of G (z/r^3, (3ab - r^2 delta)/r^5)."""
+    quadrature of G (a/r^3 for gx, gy, gz; (3ab - r^2 delta)/r^5)."""
     for box in _random_boxes(11, 40):
         k = orc.prism(*box)
         q = orc.prism_gl(*box, ratio=0.2, order=10)
         tol = 1e-12 * cancellation_factor(box)
-        scale_t = np.abs(k[1:]).max()
+        scale_t = np.abs(k[TENSOR]).max()
+        scale_g = np.abs(k[[GZ, GX, GY]]).max()
         assert abs(k[GZ] - q[GZ]) <= tol * abs(q[GZ]), box
-        assert np.all(np.abs(k[1:] - q[1:]) <= tol * scale_t), (box, k, q)
+        assert np.all(np.abs(k[TENSOR] - q[TENSOR]) <= tol * scale_t), (box, k, q)
+        assert np.all(np.abs(k[[GX, GY]] - q[[GX, GY]]) <= tol * scale_g), (box, k, q)
 
 
 # ---------------------------------------------------------------- pin 2 ----
@@ -85,6 +88,8 @@ def _point(G, m, x, y, z):
         G * m * (3 * y * y - r2) / r ** 5,
         G * m * 3 * y * z / r ** 5,
         G * m * (3 * z * z - r2) / r ** 5,
+        G * m * x / r ** 3,
+        G * m * y / r ** 3,
     ])
 
 
@@ -105,6 +110,7 @@ def test_far_field_point_mass_limit(orc, sides, slope):
         k = orc.prism(cx - ax / 2, cx + ax / 2, cy - ay / 2, cy + ay / 2, cz - az / 2, cz + az / 2)
         p = _point(G, ax * ay * az, cx, cy, cz)
         assert np.sign(k[GZ]) == 1.0
+        assert (np.sign(k[GX]), np.sign(k[GY])) == (np.sign(cx), np.sign(cy))
         errs.append(np.linalg.norm(k - p) / np.linalg.norm(p))
     fit = np.polyfit(np.log(Rs), np.log(errs), 1)[0]
     assert abs(fit - slope) < 0.2, (fit, errs)
@@ -129,20 +135,21 @@ def test_trace_free_total_field(orc):
 # ---------------------------------------------------------------- pin 4 ----
 def test_symmetry_and_parity_of_offset_table(orc):
     """Section 2.2: the field is symmetric about the X and Y axes.  gz, gxx,
-    gyy are even in a and b; gxy is odd in both; gxz odd in a, even in b; gyz
-    the reverse; swapping x and y (dx = dy) swaps gxx<->gyy, gxz<->gyz."""
+    gyy are even in a and b; gxy is odd in both; gxz and gx odd in a, even in
+    b; gyz and gy the reverse; swapping x and y (dx = dy) swaps gxx<->gyy,
+    gxz<->gyz, gx<->gy."""
     g = Geometry(12, 12, 3, 20.0, 20.0, 15.0, 7.0)
     for n in range(g.nz):
         t = orc.kernel_table(g, n)           # [c][b][a]
         fa = t[:, :, ::-1]                   # a -> -a
         fb = t[:, ::-1, :]                   # b -> -b
         for c, (sa, sb) in {GZ: (1, 1), GXX: (1, 1), GYY: (1, 1), GZZ: (1, 1),
-                            GXY: (-1, -1), GXZ: (-1, 1), GYZ: (1, -1)}.items():
+                            GXY: (-1, -1), GXZ: (-1, 1), GYZ: (1, -1), GX: (-1, 1), GY: (1, -1)}.items():
             s = np.abs(t[c]).max()
             assert np.abs(fa[c] - sa * t[c]).max() <= 4e-16 * s, c
             assert np.abs(fb[c] - sb * t[c]).max() <= 4e-16 * s, c
         tr = t.transpose(0, 2, 1)            # a <-> b
-        for c1, c2 in ((GXX, GYY), (GXZ, GYZ), (GZ, GZ), (GXY, GXY), (GZZ, GZZ)):
+        for c1, c2 in ((GXX, GYY), (GXZ, GYZ), (GZ, GZ), (GXY, GXY), (GZZ, GZZ), (GX, GY)):
             s = np.abs(t[c1]).max()
             assert np.abs(tr[c2] - t[c1]).max() <= 4e-16 * s, (c1, c2)
 
@@ -150,9 +157,10 @@ def test_symmetry_and_parity_of_offset_table(orc):
 # ---------------------------------------------------------------- pin 5 ----
 def test_tensor_is_derivative_of_gz(orc):
     """Central differences in the station position: d gz/dx0 = gxz,
-    d gz/dy0 = gyz, d gz/dz0 = gzz, d gxz/dx0 = d gxx/dz0,
-    d gxz/dy0 = d gxy/dz0, d gyz/dy0 = d gyy/dz0.  Moving the station by +e
-    moves the relative (source - station) bounds by -e."""
+    d gz/dy0 = gyz, d gz/dz0 = gzz, d gx/dx0 = gxx, d gx/dy0 = d gy/dx0 =
+    gxy, d gx/dz0 = gxz, d gy/dy0 = gyy, d gy/dz0 = gyz, d gxz/dx0 =
+    d gxx/dz0, d gxz/dy0 = d gxy/dz0, d gyz/dy0 = d gyy/dz0.  Moving the
+    station by +e moves the relative (source - station) bounds by -e."""
     for box in _random_boxes(13, 12):
         x1, x2, y1, y2, z1, z2 = box
         e = 1e-4 * z1  # truncation ~ (e / nearest distance)^2
@@ -164,10 +172,12 @@ def test_tensor_is_derivative_of_gz(orc):
         dY = (k(dy=e) - k(dy=-e)) / (2 * e)
         dZ = (k(dz=e) - k(dz=-e)) / (2 * e)
         k0 = k()
-        st = np.abs(k0[1:]).max()
-        for got, want in ((dX[GZ], k0[GXZ]), (dY[GZ], k0[GYZ]), (dZ[GZ], k0[GZZ])):
+        st = np.abs(k0[TENSOR]).max()
+        for got, want in ((dX[GZ], k0[GXZ]), (dY[GZ], k0[GYZ]), (dZ[GZ], k0[GZZ]),
+                          (dX[GX], k0[GXX]), (dY[GX], k0[GXY]), (dZ[GX], k0[GXZ]),
+                          (dX[GY], k0[GXY]), (dY[GY], k0[GYY]), (dZ[GY], k0[GYZ])):
             assert abs(got - want) <= 1e-6 * st, (box, got, want)
-        s3 = max(np.abs(dX).max(), np.abs(dY).max(), np.abs(dZ).max())
+        s3 = max(np.abs(dX[TENSOR]).max(), np.abs(dY[TENSOR]).max(), np.abs(dZ[TENSOR]).max())
         for got, want in ((dX[GXZ], dZ[GXX]), (dY[GXZ], dZ[GXY]), (dY[GYZ], dZ[GYY]),
                           (dX[GXY], dY[GXX]), (dY[GXY], dX[GYY])):
             assert abs(got - want) <= 1e-6 * s3, (box, got, want)
@@ -185,7 +195,7 @@ def test_cells_sum_to_merged_prism(orc):
     st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
     want = orc.blocks_at_stations(g, blocks, st)
     got = orc.forward(g, rho, st)
-    for c in range(7):
+    for c in range(orc.NCOMP):
         assert rel(got[:, c], want[:, c]) <= 1e-12, c
 
 
@@ -214,7 +224,7 @@ def test_dense_matrix_structure(orc):
     dense matrix is built from absolute positions; the offset table from
     offsets alone."""
     g = Geometry(5, 4, 3, 20.0, 30.0, 25.0, 10.0)
-    for comp in (GZ, GXY, GXZ, GYZ):
+    for comp in (GZ, GXY, GXZ, GYZ, GX, GY):
         Gm = orc.dense_matrix(g, comp)                      # [i][j]
         G5 = Gm.reshape(g.ny, g.nx, g.nz, g.ny, g.nx)       # [q][p][n][m][l]
         s = np.abs(Gm).max()
@@ -235,14 +245,14 @@ def fft_from_tables(g, rho, tables, px, py):
     """Library-FFT form of eq. 18 on the oracle's tables: each layer's table is
     placed circularly on a Py x Px grid (offset a at index a mod Px); the
     density is zero-padded; d = IDFT2(conj(DFT2(K)) DFT2(rho))[:ny,:nx]."""
-    out = np.zeros((7, g.ny, g.nx))
+    out = np.zeros((len(tables[0]), g.ny, g.nx))
     a = np.arange(-(g.nx - 1), g.nx) % px
     b = np.arange(-(g.ny - 1), g.ny) % py
     for n in range(g.nz):
         rp = np.zeros((py, px))
         rp[:g.ny, :g.nx] = rho[n]
         rh = np.fft.fft2(rp)
-        for c in range(7):
+        for c in range(len(tables[n])):
             emb = np.zeros((py, px))
             emb[np.ix_(b, a)] = tables[n][c]
             out[c] += np.real(np.fft.ifft2(np.conj(np.fft.fft2(emb)) * rh))[:g.ny, :g.nx]
@@ -261,7 +271,7 @@ def test_circulant_embedding_equals_direct_sum(orc, geom, pad):
     px, py = 2 * geom.nx + pad[0], 2 * geom.ny + pad[1]
     got = fft_from_tables(geom, rho, tables, px, py)
     want = orc.forward_grid(geom, rho)
-    for c in range(7):
+    for c in range(orc.NCOMP):
         assert rel(got[c], want[c]) <= 1e-14, c
 
 
@@ -270,14 +280,15 @@ def test_adjoint_dot_product_and_dense_transpose(orc):
     g = Geometry(6, 5, 3, 20.0, 25.0, 15.0, 9.0)
     rng = np.random.default_rng(7)
     m = rng.standard_normal((g.nz, g.ny, g.nx)) * 500
-    r = rng.standard_normal((7, g.ny, g.nx))
-    mask = 0b0111111  # the six stored components
+    r = rng.standard_normal((orc.NCOMP, g.ny, g.nx))
+    comps = [GZ, GXX, GXY, GXZ, GYY, GYZ, GX, GY]  # every independent component
+    mask = sum(1 << c for c in comps)
     d = orc.forward_grid(g, m)
-    lhs = sum(np.vdot(d[c], r[c]) for c in range(6))
+    lhs = sum(np.vdot(d[c], r[c]) for c in comps)
     gt = orc.adjoint(g, r, mask)
     rhs = np.vdot(m, gt)
-    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(d[:6]) * np.linalg.norm(r[:6])
-    want = sum(orc.dense_matrix(g, c).T @ r[c].ravel() for c in range(6))
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(d[comps]) * np.linalg.norm(r[comps])
+    want = sum(orc.dense_matrix(g, c).T @ r[c].ravel() for c in comps)
     assert rel(gt.ravel(), want) <= 1e-14
     # cells listed one by one give the same numbers
     cells = np.array([(1, 2, 0), (5, 4, 2), (0, 0, 1)])
@@ -329,12 +340,12 @@ def test_paper_validation_model(orc):
 
     st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
     merged = orc.blocks_at_stations(g, [(17, 23, 17, 23, 10, 16, 300.0)], st)
-    merged = merged.reshape(g.ny, g.nx, 7).transpose(2, 0, 1)
+    merged = merged.reshape(g.ny, g.nx, orc.NCOMP).transpose(2, 0, 1)
     tables = [orc.kernel_table(g, n) for n in range(10, 16)]
     sub = Geometry(g.nx, g.ny, 6, g.dx, g.dy, g.dz, g.h + 10 * g.dz)
     fast = fft_from_tables(sub, rho[10:16], [orc.kernel_table(sub, n) for n in range(6)],
                            2 * g.nx, 2 * g.ny)
-    for c in range(7):
+    for c in range(orc.NCOMP):  # Fig. 6-7 include the first derivatives gx, gy
         assert rel(fast[c], merged[c]) <= 10.0 ** -fx["residual_orders"][0], c
     # the layered tables equal the shifted-geometry tables (same prisms)
     for n in range(6):
