@@ -15,9 +15,11 @@
  * Geometry (section 2.1): nx*ny*nz cells of dx*dy*dz metres, z down, top of
  * the model at depth 0; one station above the centre of each surface cell at
  * height h > 0.  Components: gz and the five independent tensor components
- * gxx, gxy, gxz, gyy, gyz (eq. 1); gzz = -(gxx+gyy) is derived.
+ * gxx, gxy, gxz, gyy, gyz (eq. 1); gzz = -(gxx+gyy) is derived; and the
+ * horizontal first derivatives gx, gy of the potential, whose kernel
+ * matrices are BTTB as well (section 2.2.3; section 3.1 shows all nine).
  *
- * Units: density in kg/m^3; gz in m/s^2; tensor components in 1/s^2.  The
+ * Units: density in kg/m^3; gz, gx, gy in m/s^2; tensor components in 1/s^2.  The
  * gravitational constant is 6.672e-11 N m^2/kg^2 (eq. 2).
  *
  * Layouts (x fastest, section 2.2's cell numbering):
@@ -70,8 +72,11 @@ enum {
     GF_GYY = 1u << 4,
     GF_GYZ = 1u << 5,
     GF_GZZ = 1u << 6,     /* derived: -(gxx + gyy) */
+    GF_GX = 1u << 7,
+    GF_GY = 1u << 8,
     GF_ALL6 = 0x3Fu,
-    GF_ALL7 = 0x7Fu
+    GF_ALL7 = 0x7Fu,
+    GF_ALL9 = 0x1FFu      /* gz, the six tensor components, gx, gy */
 };
 
 typedef enum {
@@ -86,8 +91,8 @@ enum { GF_OP_FORWARD = 0, GF_OP_ADJOINT = 1 };
 typedef struct {
     int nx, ny, nz;
     int px, py;            /* circulant sizes: powers of two >= 2n-1 (eq. 10-11) */
-    int n_out;             /* C: number of output components                    */
-    int n_spec;            /* number of resident spectral components            */
+    int n_out;             /* C: number of output components (<= 9)             */
+    int n_spec;            /* number of resident spectral components (<= 8)     */
     unsigned components;   /* output mask                                       */
     unsigned spec_mask;    /* components whose spectra are resident             */
     int precision;         /* gf_precision                                      */
@@ -106,12 +111,15 @@ typedef struct {
  * resident: one real per frequency on the quarter plane
  * kx in [0, Px/2], ky in [0, Py/2], since the spectrum of each component is
  * purely real or purely imaginary and even or odd in each frequency axis
- * (the potential-field symmetry of section 2.2).
+ * (the potential-field symmetry of section 2.2).  Every output component
+ * except gzz has its own spectrum; gzz reuses those of gxx and gyy.  Plans
+ * with more than six spectra (gx or gy with the full tensor) run the column
+ * pass once per group of up to six.
  *
  *   nx, ny, nz  >= 1, nx, ny <= 2048           grid size
  *   dx, dy, dz  > 0                            cell size, metres
  *   h           > 0                            station height above the top
- *   components  nonzero subset of GF_ALL7
+ *   components  nonzero subset of GF_ALL9
  *   precision   GF_F64 or GF_F32
  *   max_batch   >= 0: size of an internal workspace for up to max_batch
  *               models (0 = none; callers then pass their own workspace)
@@ -180,17 +188,18 @@ const char *gf_last_error(void);
 /*
  * Test access to plan-time intermediates (synchronous; slow).
  * Kernel table of layer n as generated on the device, copied to host:
- * host_out[7][2ny-1][2nx-1] with index [c][b+ny-1][a+nx-1], component order
- * gz, gxx, gxy, gxz, gyy, gyz, gzz (gzz = -(gxx+gyy) from the generated
- * values); it is generated for all six components whatever the plan's mask.
+ * host_out[9][2ny-1][2nx-1] with index [c][b+ny-1][a+nx-1], component order
+ * gz, gxx, gxy, gxz, gyy, gyz, gzz, gx, gy (gzz = -(gxx+gyy) from the
+ * generated values); it is generated for every component whatever the
+ * plan's mask.
  */
 gf_status gf_debug_kernel_table(const gf_plan *plan, int n, double *host_out);
 
 /* Resident quarter-plane spectrum of component bit `component` (one of the
  * plan's spectral components) in layer n, copied to host as double:
  * host_out[Px/2+1][Py/2+1] with index [kx][ky]; the real part for
- * gz, gxx, gxy, gyy, the imaginary part for gxz, gyz (unit gravitational
- * constant). */
+ * gz, gxx, gxy, gyy, the imaginary part for gxz, gyz, gx, gy (unit
+ * gravitational constant). */
 gf_status gf_debug_spectrum(const gf_plan *plan, unsigned component, int n, double *host_out);
 
 #ifdef __cplusplus

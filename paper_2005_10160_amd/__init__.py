@@ -11,10 +11,13 @@ gfx950 in ``libgravfft.so`` behind the C ABI of ``include/gravfft.h``.
 from .operator import (
     ALL6,
     ALL7,
+    ALL9,
     COMPONENTS,
     GXX,
     GXY,
+    GX,
     GXZ,
+    GY,
     GYY,
     GYZ,
     GZ,
@@ -29,7 +32,7 @@ from .operator import (
 )
 
 __all__ = [
-    "ALL6", "ALL7", "COMPONENTS", "GZ", "GXX", "GXY", "GXZ", "GYY", "GYZ", "GZZ",
+    "ALL6", "ALL7", "ALL9", "COMPONENTS", "GZ", "GXX", "GXY", "GXZ", "GYY", "GYZ", "GZZ", "GX", "GY",
     "GravityForward", "GravityOperator", "Plan", "adjoint", "components_mask",
     "forward", "plan",
 ]

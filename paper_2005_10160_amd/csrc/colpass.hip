@@ -234,7 +234,7 @@ template <typename T, int N, int CMAX, int KIND>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     __attribute__((amdgpu_waves_per_eu(ColCfg<T, N>::WAVES_PER_EU)))
     col_forward_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec,
-                       cx<T> *__restrict__ D, int B, int nz, int M, int ny, int ldc, int Cs, int lps,
+                       cx<T> *__restrict__ D, int B, int nz, int M, int ny, int ldc, int Cs, int Ct, int lps,
                        unsigned imag_mask, unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
 {
     using C = ColCfg<T, N>;
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
             out_to_in<F, T, PPT>(acc[c]);
             F::template run<true>(acc[c], xbuf, xim, t, twp, twlog);
             if (w.active)
-                store_column<T, PPT, F, NT>(D + ((((size_t)split * B + w.b) * Cs + c) * M + w.u) * (size_t)ldc,
+                store_column<T, PPT, F, NT>(D + ((((size_t)split * B + w.b) * Ct + c) * M + w.u) * (size_t)ldc,
                                             acc[c], t, ny, w.part);
         }
     }
@@ -333,7 +333,7 @@ template <typename T, int N, int CMAX, int KIND>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     __attribute__((amdgpu_waves_per_eu(ColCfg<T, N>::WAVES_PER_EU)))
     col_adjoint_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec,
-                       cx<T> *__restrict__ Gout, int B, int nz, int M, int ny, int ldc, int Cs, int lps,
+                       cx<T> *__restrict__ Gout, int B, int nz, int M, int ny, int ldc, int Cs, int Ct, int lps,
                        unsigned imag_mask, unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
 {
     using C = ColCfg<T, N>;
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
         for (int s = 0; s < PPT; ++s) rh[c][s] = cx<T>{T(0), T(0)};
         if (c < Cs) {  // unconditional loads from clamped rows, selected after
-            const cx<T> *col = column(R, (size_t)w.b * Cs + c, M, w.u, ldc);
+            const cx<T> *col = column(R, (size_t)w.b * Ct + c, M, w.u, ldc);
 #pragma unroll
             for (int s = 0; s < PPT; ++s) {
                 const unsigned y = t + NT * F::elem_in(s);
@@ -762,7 +762,7 @@ template <typename T, int N, int CMAX, int KIND>
 __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     __attribute__((amdgpu_waves_per_eu(WsCfg<T, N>::WAVES_PER_EU)))
     col_forward_ws_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec, cx<T> *__restrict__ D,
-                          T *__restrict__ Dny, int B, int nz, int M, int ny, int ldc, int Cs, int lps,
+                          T *__restrict__ Dny, int B, int nz, int M, int ny, int ldc, int Cs, int Ct, int lps,
                           int nblk_ny, int Sny, int lps_ny, int nblk_main, unsigned imag_mask,
                           unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
 {
@@ -858,11 +858,11 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             if (un.active) {
                 if (un.nyq)   // real partial column of the Nyquist unit
                     ws_store<T, N, NW, L, PPT, GT>(
-                        cre, reinterpret_cast<cx<T> *>(Dny + (((size_t)un.split * B + un.b) * Cs + c) * (size_t)ldc),
+                        cre, reinterpret_cast<cx<T> *>(Dny + (((size_t)un.split * B + un.b) * Ct + c) * (size_t)ldc),
                         tg, ny, 3);
                 else
                     ws_store<T, N, NW, L, PPT, GT>(
-                        cre, D + ((((size_t)un.split * B + un.b) * Cs + c) * M + un.u) * (size_t)ldc, tg, ny, un.part);
+                        cre, D + ((((size_t)un.split * B + un.b) * Ct + c) * M + un.u) * (size_t)ldc, tg, ny, un.part);
             }
             lds_barrier();
         }
@@ -876,7 +876,7 @@ template <typename T, int N, int CMAX, int KIND>
 __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     __attribute__((amdgpu_waves_per_eu(WsCfg<T, N>::WAVES_PER_EU)))
     col_adjoint_ws_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec, cx<T> *__restrict__ Gout,
-                          int B, int nz, int M, int ny, int ldc, int Cs, int lps, int nblk_ny, int Sny,
+                          int B, int nz, int M, int ny, int ldc, int Cs, int Ct, int lps, int nblk_ny, int Sny,
                           int lps_ny, int nblk_main, unsigned imag_mask, unsigned yodd_mask,
                           const cx<T> *__restrict__ tw, int twlog)
 {
@@ -924,7 +924,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
         if (c < Cs) {
             for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) rbuf[c * (N / 2) + i] = cx<T>{T(0), T(0)};
             cx<T> tail{T(0), T(0)};
-            stage_column<T, GT>(column(R, (size_t)un.b * Cs + c, M, un.u, ldc), rbuf + c * (N / 2), ny, tg, tail);
+            stage_column<T, GT>(column(R, (size_t)un.b * Ct + c, M, un.u, ldc), rbuf + c * (N / 2), ny, tg, tail);
             put_tail(rbuf + c * (N / 2), ny, tg, tail);
         }
     }
@@ -1034,7 +1034,7 @@ __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
 
 template <typename T, int N, int CMAX, int KIND>
 static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc, int Cs,
-                   int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
+                   int Ct, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
                    const void *tw, int twlog, hipStream_t st)
 {
     if constexpr (use_ws<N>()) {
@@ -1046,7 +1046,7 @@ static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int 
         if (nq.Sny < 1 || nq.lps_ny < 1 || !nq.Dny) return -2;
         hipLaunchKernelGGL((col_forward_ws_kernel<T, N, CMAX, KIND>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
-                           (T *)nq.Dny, B, nz, M, ny, ldc, Cs, lps, (int)nblk_ny, nq.Sny, nq.lps_ny,
+                           (T *)nq.Dny, B, nz, M, ny, ldc, Cs, Ct, lps, (int)nblk_ny, nq.Sny, nq.lps_ny,
                            (int)nblk_main, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
     } else {
         using C = ColCfg<T, N>;
@@ -1056,14 +1056,14 @@ static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int 
         if (lds > lds_limit()) return -3;
         hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
-                           B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+                           B, nz, M, ny, ldc, Cs, Ct, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T, int N, int CMAX, int KIND>
 static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc, int Cs,
-                   int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
+                   int Ct, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
                    const void *tw, int twlog, hipStream_t st)
 {
     if constexpr (use_ws<N>()) {
@@ -1075,7 +1075,7 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
         if (nq.Sny < 1 || nq.lps_ny < 1) return -2;
         hipLaunchKernelGGL((col_adjoint_ws_kernel<T, N, CMAX, KIND>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)Gout, B, nz,
-                           M, ny, ldc, Cs, lps, (int)nblk_ny, nq.Sny, nq.lps_ny, (int)nblk_main, imag_mask,
+                           M, ny, ldc, Cs, Ct, lps, (int)nblk_ny, nq.Sny, nq.lps_ny, (int)nblk_main, imag_mask,
                            yodd_mask, (const cx<T> *)tw, twlog);
     } else {
         using C = ColCfg<T, N>;
@@ -1085,7 +1085,7 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
         if (lds > lds_limit()) return -3;
         hipLaunchKernelGGL((col_adjoint_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec,
-                           (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, lps, imag_mask, yodd_mask,
+                           (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, Ct, lps, imag_mask, yodd_mask,
                            (const cx<T> *)tw, twlog);
     }
     return hipGetLastError() == hipSuccess ? 0 : -1;
@@ -1115,44 +1115,44 @@ constexpr unsigned KIND_FULL6_YO = (1u << 2) | (1u << 5);
 constexpr int KIND_FULL6 = (int)(KIND_FULL6_IM | (KIND_FULL6_YO << 8));
 
 template <typename T, int N>
-static int fwd_c(int Cs, const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc,
+static int fwd_c(int Cs, int Ct, const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc,
                  int nsplit, int lps, const NyqSplit &nq, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
     if (Cs == 6 && im == KIND_FULL6_IM && yo == KIND_FULL6_YO)
-        return run_fwd<T, N, 6, KIND_FULL6>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+        return run_fwd<T, N, 6, KIND_FULL6>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
     if (Cs == 1 && im == 0 && yo == 0)
-        return run_fwd<T, N, 1, 0>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
-    if (Cs <= 1) return run_fwd<T, N, 1, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_fwd<T, N, 3, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
-    return run_fwd<T, N, 6, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+        return run_fwd<T, N, 1, 0>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_fwd<T, N, 1, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_fwd<T, N, 3, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
+    return run_fwd<T, N, 6, -1>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
 }
 
 template <typename T, int N>
-static int adj_c(int Cs, const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc,
+static int adj_c(int Cs, int Ct, const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc,
                  int nsplit, int lps, const NyqSplit &nq, unsigned im, unsigned yo, const void *tw, int twlog,
                  hipStream_t st)
 {
     if (Cs == 6 && im == KIND_FULL6_IM && yo == KIND_FULL6_YO)
-        return run_adj<T, N, 6, KIND_FULL6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+        return run_adj<T, N, 6, KIND_FULL6>(R, spec, Gout, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
     if (Cs == 1 && im == 0 && yo == 0)
-        return run_adj<T, N, 1, 0>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
-    if (Cs <= 1) return run_adj<T, N, 1, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
-    if (Cs <= 3) return run_adj<T, N, 3, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
-    return run_adj<T, N, 6, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nsplit, lps, nq, im, yo, tw, twlog, st);
+        return run_adj<T, N, 1, 0>(R, spec, Gout, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 1) return run_adj<T, N, 1, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
+    if (Cs <= 3) return run_adj<T, N, 3, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
+    return run_adj<T, N, 6, -1>(R, spec, Gout, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq, im, yo, tw, twlog, st);
 }
 
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
-                       int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask,
+                       int M, int ny, int ldc, int Cs, int Ct, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
     // the kernels skip the upper half of each column (zero padding)
-    if (Cs < 1 || Cs > 6 || ny < 1 || 2 * ny > py || ldc < ny) return -2;
+    if (Cs < 1 || Cs > 6 || Ct < Cs || ny < 1 || 2 * ny > py || ldc < ny) return -2;
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
-        return fp64 ? fwd_c<double, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,    \
+        return fp64 ? fwd_c<double, NN>(Cs, Ct, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,    \
                                         yodd_mask, tw, twlog, st)                                \
-                    : fwd_c<float, NN>(Cs, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,     \
+                    : fwd_c<float, NN>(Cs, Ct, R, spec, D, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,     \
                                        yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
@@ -1163,15 +1163,15 @@ int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void 
 }
 
 int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
-                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask,
+                       int nz, int M, int ny, int ldc, int Cs, int Ct, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask,
                        unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
 {
-    if (Cs < 1 || Cs > 6 || ny < 1 || 2 * ny > py || ldc < ny) return -2;   // upper half of columns skipped
+    if (Cs < 1 || Cs > 6 || Ct < Cs || ny < 1 || 2 * ny > py || ldc < ny) return -2;   // upper half of columns skipped
 #define CASE(NN)                                                                                 \
     case NN:                                                                                     \
-        return fp64 ? adj_c<double, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask, \
+        return fp64 ? adj_c<double, NN>(Cs, Ct, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask, \
                                         yodd_mask, tw, twlog, st)                                \
-                    : adj_c<float, NN>(Cs, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,  \
+                    : adj_c<float, NN>(Cs, Ct, R, spec, Gout, B, nz, M, ny, ldc, nsplit, lps, nq, imag_mask,  \
                                        yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)

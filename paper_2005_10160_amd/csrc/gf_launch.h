@@ -6,19 +6,25 @@
 
 namespace gf {
 
+// Most output components of one plan (gz, the six tensor components, gx, gy)
+// and most spectra one column-pass launch carries; plans with more resident
+// spectra run the column pass once per group of at most kColMaxSpec.
+constexpr int kMaxOut = 9;
+constexpr int kColMaxSpec = 6;
+
 // How a slab of rows is formed from source slabs: slab s of batch item b is
 // sum_i w[s][i] * src_slab(b, src[s][i]).  identity: slab s reads source s.
 struct RowCombo {
     int identity;
-    int nterm[8];
-    int src[8][2];
-    double w[8][2];
+    int nterm[kMaxOut];
+    int src[kMaxOut][2];
+    double w[kMaxOut][2];
 };
 
 // Layer chunks of the real Nyquist unit (kx = px/2) when the column passes
 // run it apart from the main units (col_nyquist_apart): Sny chunks of lps_ny
 // layers; the forward pass writes its partial columns to
-// Dny[Sny][B][Cs][ldc] (real values), summed by the inverse row pass.
+// Dny[Sny][B][Ct][ldc] (real values), summed by the inverse row pass.
 struct NyqSplit {
     void *Dny;
     int Sny, lps_ny;
@@ -69,15 +75,19 @@ bool col_nyquist_apart(int py);
 
 // Column pass of the forward operator: per column unit u and model b, for
 // each layer n of the split: FFT along y, multiply by conj(K^_{c,n}) and
-// accumulate over n; then inverse FFT per component.
+// accumulate over n; then inverse FFT per component.  spec holds Cs
+// (<= kColMaxSpec) components; D (and nq.Dny) are laid out with a slot
+// stride of Ct >= Cs components, the caller offsetting them to the group's
+// first slot.
 int launch_col_forward(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz,
-                       int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq,
+                       int M, int ny, int ldc, int Cs, int Ct, int nsplit, int lps, const NyqSplit &nq,
                        unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
 // Column pass of the adjoint: FFT of the Cs residual columns, then per layer
-// sum_c K^_{c,n} r^_c and an inverse FFT.
+// sum_c K^_{c,n} r^_c and an inverse FFT.  R is laid out with a slot stride
+// of Ct >= Cs components (offset by the caller to the group's first slot).
 int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void *Gout, int B,
-                       int nz, int M, int ny, int ldc, int Cs, int nsplit, int lps, const NyqSplit &nq,
+                       int nz, int M, int ny, int ldc, int Cs, int Ct, int nsplit, int lps, const NyqSplit &nq,
                        unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
 // Plan time: column FFT of the row-transformed kernel fields and extraction

@@ -86,9 +86,9 @@ gf::GLRules make_rules()
     return r;
 }
 
-// component codes: 0 gz, 1 gxx, 2 gxy, 3 gxz, 4 gyy, 5 gyz, 6 gzz
-bool is_imag(int code) { return code == 3 || code == 5; }   // odd in exactly one of x, y
-bool is_yodd(int code) { return code == 2 || code == 5; }   // odd in y
+// component codes: 0 gz, 1 gxx, 2 gxy, 3 gxz, 4 gyy, 5 gyz, 6 gzz, 7 gx, 8 gy
+bool is_imag(int code) { return code == 3 || code == 5 || code == 7 || code == 8; }   // odd in exactly one of x, y
+bool is_yodd(int code) { return code == 2 || code == 5 || code == 8; }                // odd in y
 
 struct DevBuf {
     void *p = nullptr;
@@ -109,11 +109,16 @@ struct gf_plan {
     int px, py, M, U, Q, QP, twlog; // M column units; U = M + 1 spectral rows of QP values
     int ldc;                        // leading dimension of column layouts (even)
     int n_out;
-    int out_codes[7];
+    int out_codes[gf::kMaxOut];
     int n_spec;
-    int spec_codes[6];
+    int spec_codes[8];
     unsigned spec_mask;
     unsigned imag_mask, yodd_mask;  // over spectral slots
+    // Spectral slots in groups of at most kColMaxSpec, one column-pass
+    // launch each; group g holds slots [grp_c0[g], grp_c0[g] + grp_cs[g]) and
+    // its spectra are stored apart as [nz][M+1][grp_cs[g]][QP].
+    int ngrp;
+    int grp_c0[2], grp_cs[2];
     gf::RowCombo out_combo;         // output o from spectral slots
     gf::RowCombo in_combo;          // adjoint: spectral slot s from input components
     void *spec = nullptr;
@@ -129,6 +134,8 @@ struct gf_plan {
     bool ev_recorded[2] = {false, false};
 
     bool fp64() const { return prec == GF_F64; }
+    char *spec_group(int g) const { return (char *)spec + elem() * (size_t)nz * U * QP * grp_c0[g]; }
+    unsigned grp_bits(unsigned m, int g) const { return (m >> grp_c0[g]) & ((1u << grp_cs[g]) - 1u); }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
     size_t celem() const { return 2 * elem(); }
     int slot_of(int code) const
@@ -172,7 +179,7 @@ struct gf_plan {
     {
         const int G = gf::col_forward_groups(fp64(), py);
         const long nblk = (main_units() + G - 1) / G;
-        const int cap = gf::col_forward_capacity(fp64(), py, n_spec, 1);
+        const int cap = gf::col_forward_capacity(fp64(), py, grp_cs[0], 1);
         // cost in units of one layer of one round of resident workgroups;
         // each split adds a partial-sum write and read (~beta layers)
         const double per_layer = (double)n_spec * Q + 2.0 * ny;
@@ -196,7 +203,7 @@ struct gf_plan {
     {
         const int G = gf::col_forward_groups(fp64(), py);
         const long nblk = (main_units() * B + G - 1) / G;
-        const int cap = gf::col_forward_capacity(fp64(), py, n_spec, B);
+        const int cap = gf::col_forward_capacity(fp64(), py, grp_cs[0], B);
         long s = (2L * cap + nblk - 1) / nblk;
         if (s < 1) s = 1;
         if (s > nz) s = nz;
@@ -212,7 +219,7 @@ struct gf_plan {
             fwd_split(B, &S, &l);
             return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * n_spec) + nyq_bytes(B);
         }
-        return celem() * (size_t)M * ldc * ((size_t)B * n_spec + (size_t)B * nz);
+        return celem() * (size_t)M * ldc * ((size_t)B * n_spec + (size_t)ngrp * B * nz);
     }
 };
 
@@ -261,33 +268,37 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
     const size_t field = (size_t)p->py * p->px;
     const size_t per_pair = field * sizeof(double) + (size_t)p->M * p->py * 2 * sizeof(double);
     const size_t budget = (size_t)2 << 30;
-    int nl = (int)(budget / (per_pair * p->n_spec));
+    int nl = (int)(budget / (per_pair * p->grp_cs[0]));
     if (nl < 1) nl = 1;
     if (nl > p->nz) nl = p->nz;
     DevBuf E, Rk;
     gf_status s;
-    if ((s = hip_check(hipMalloc(&E.p, field * sizeof(double) * nl * p->n_spec), "kernel field")) != GF_OK)
+    if ((s = hip_check(hipMalloc(&E.p, field * sizeof(double) * nl * p->grp_cs[0]), "kernel field")) != GF_OK)
         return s;
-    if ((s = hip_check(hipMalloc(&Rk.p, (size_t)p->M * p->py * 2 * sizeof(double) * nl * p->n_spec),
+    if ((s = hip_check(hipMalloc(&Rk.p, (size_t)p->M * p->py * 2 * sizeof(double) * nl * p->grp_cs[0]),
                        "kernel row spectra")) != GF_OK)
         return s;
     const gf::KgenGeom g = kgen_geom(p);
     const gf::GLRules gl = make_rules();
     gf::RowCombo ident{};
     ident.identity = 1;
-    for (int n0 = 0; n0 < p->nz; n0 += nl) {
-        const int nlc = std::min(nl, p->nz - n0);
-        const int npair = nlc * p->n_spec;
-        if ((s = hip_check(hipMemsetAsync(E.p, 0, field * sizeof(double) * npair, st), "memset")) != GF_OK)
-            return s;
-        if (gf::launch_kgen_field(E.p, nlc, n0, p->n_spec, p->spec_codes, g, gl, st) != 0)
-            return fail(GF_EDEVICE, "kernel table launch failed");
-        if (gf::launch_row_r2c(true, p->px, E.p, p->px, p->px, p->py, p->py, npair, npair, 1, ident, Rk.p,
-                               p->tw64, p->twlog, st) != 0)
-            return fail(GF_EDEVICE, "kernel row transform launch failed");
-        if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec, nlc, n0, p->n_spec, p->nz, p->M,
-                                p->imag_mask, p->yodd_mask, p->tw64, p->twlog, st) != 0)
-            return fail(GF_EDEVICE, "kernel column transform launch failed");
+    for (int gr = 0; gr < p->ngrp; ++gr) {
+        const int cs = p->grp_cs[gr];
+        for (int n0 = 0; n0 < p->nz; n0 += nl) {
+            const int nlc = std::min(nl, p->nz - n0);
+            const int npair = nlc * cs;
+            if ((s = hip_check(hipMemsetAsync(E.p, 0, field * sizeof(double) * npair, st), "memset")) != GF_OK)
+                return s;
+            if (gf::launch_kgen_field(E.p, nlc, n0, cs, p->spec_codes + p->grp_c0[gr], g, gl, st) != 0)
+                return fail(GF_EDEVICE, "kernel table launch failed");
+            if (gf::launch_row_r2c(true, p->px, E.p, p->px, p->px, p->py, p->py, npair, npair, 1, ident, Rk.p,
+                                   p->tw64, p->twlog, st) != 0)
+                return fail(GF_EDEVICE, "kernel row transform launch failed");
+            if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec_group(gr), nlc, n0, cs, p->nz, p->M,
+                                    p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr), p->tw64,
+                                    p->twlog, st) != 0)
+                return fail(GF_EDEVICE, "kernel column transform launch failed");
+        }
     }
     return hip_check(hipStreamSynchronize(st), "plan synchronise");
 }
@@ -344,7 +355,8 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
         return fail(GF_EINVAL, "cell sizes must be positive and finite");
     if (!(h > 0) || !std::isfinite(h)) return fail(GF_EINVAL, "station height h must be > 0");
-    if (components == 0 || (components & ~0x7Fu)) return fail(GF_EINVAL, "bad component mask 0x%x", components);
+    if (components == 0 || (components & ~(unsigned)GF_ALL9))
+        return fail(GF_EINVAL, "bad component mask 0x%x", components);
     if (precision != GF_F64 && precision != GF_F32) return fail(GF_EINVAL, "bad precision %d", precision);
     if (max_batch < 0) return fail(GF_EINVAL, "max_batch must be >= 0");
     if ((long)nz * nx * ny > (1L << 31)) return fail(GF_EUNSUPPORTED, "model too large");
@@ -375,23 +387,28 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     (void)hipGetDevice(&p->device);
 
     p->n_out = 0;
-    for (int c = 0; c < 7; ++c)
+    for (int c = 0; c < gf::kMaxOut; ++c)
         if (components & (1u << c)) p->out_codes[p->n_out++] = c;
-    p->spec_mask = components & 0x3Fu;
+    p->spec_mask = components & ~(unsigned)GF_GZZ;
     if (components & GF_GZZ) p->spec_mask |= GF_GXX | GF_GYY;
     p->n_spec = 0;
     p->imag_mask = p->yodd_mask = 0;
-    for (int c = 0; c < 6; ++c)
+    for (int c = 0; c < gf::kMaxOut; ++c)
         if (p->spec_mask & (1u << c)) {
             const int s = p->n_spec++;
             p->spec_codes[s] = c;
             if (is_imag(c)) p->imag_mask |= 1u << s;
             if (is_yodd(c)) p->yodd_mask |= 1u << s;
         }
+    p->ngrp = (p->n_spec + gf::kColMaxSpec - 1) / gf::kColMaxSpec;
+    for (int g = 0; g < p->ngrp; ++g) {
+        p->grp_c0[g] = g * gf::kColMaxSpec;
+        p->grp_cs[g] = std::min(gf::kColMaxSpec, p->n_spec - p->grp_c0[g]);
+    }
     std::memset(&p->out_combo, 0, sizeof(p->out_combo));
     for (int o = 0; o < p->n_out; ++o) {
         const int code = p->out_codes[o];
-        if (code < 6) {
+        if (code != 6) {
             p->out_combo.nterm[o] = 1;
             p->out_combo.src[o][0] = p->slot_of(code);
             p->out_combo.w[o][0] = 1.0;
@@ -447,10 +464,12 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
             }
         }
     }
-    if (!gf::col_supported(p->fp64(), p->py, p->n_spec)) {
-        free_plan(p);
-        return fail(GF_EUNSUPPORTED, "transform length %d with %d components does not fit in LDS", p->py, p->n_spec);
-    }
+    for (int g = 0; g < p->ngrp; ++g)
+        if (!gf::col_supported(p->fp64(), p->py, p->grp_cs[g])) {
+            free_plan(p);
+            return fail(GF_EUNSUPPORTED, "transform length %d with %d components does not fit in LDS", p->py,
+                        p->grp_cs[g]);
+        }
     p->spec_bytes = (size_t)nz * p->U * p->n_spec * p->QP * p->elem();
     if ((s = hip_check(hipMalloc(&p->spec, p->spec_bytes), "spectra")) != GF_OK) {
         free_plan(p);
@@ -546,9 +565,16 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
                            p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 1, st);
-    if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec, D, batch, p->nz, p->M, p->ny, p->ldc, p->n_spec, S, lps,
-                               nq, p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
-        return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+    for (int gr = 0; gr < p->ngrp; ++gr) {
+        const int c0 = p->grp_c0[gr];
+        gf::NyqSplit nqg = nq;
+        if (nqg.Dny) nqg.Dny = (char *)nqg.Dny + p->elem() * (size_t)c0 * p->ldc;
+        if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec_group(gr), D + p->celem() * (size_t)c0 * p->M * p->ldc,
+                                   batch, p->nz, p->M, p->ny, p->ldc, p->grp_cs[gr], p->n_spec, S, lps, nqg,
+                                   p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr), p->tw, p->twlog,
+                                   st) != 0)
+            return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+    }
     mark(p, GF_OP_FORWARD, 2, st);
     const double scale = kGrav / ((double)p->py * p->M);
     if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->M * p->ldc, S, p->n_spec, p->ny,
@@ -577,16 +603,24 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
                            p->in_combo, R, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 1, st);
-    if (gf::launch_col_adjoint(p->fp64(), p->py, R, p->spec, Gt, batch, p->nz, p->M, p->ny, p->ldc, p->n_spec, S, lps,
-                               nq, p->imag_mask, p->yodd_mask, p->tw, p->twlog, st) != 0)
-        return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+    // each group writes its own layer columns; the inverse row pass sums the
+    // groups as it sums split partials
+    const size_t gstride = (size_t)batch * p->nz * p->M * p->ldc;
+    for (int gr = 0; gr < p->ngrp; ++gr) {
+        const int c0 = p->grp_c0[gr];
+        if (gf::launch_col_adjoint(p->fp64(), p->py, R + p->celem() * (size_t)c0 * p->M * p->ldc, p->spec_group(gr),
+                                   Gt + p->celem() * gr * gstride, batch, p->nz, p->M, p->ny, p->ldc, p->grp_cs[gr],
+                                   p->n_spec, S, lps, nq, p->grp_bits(p->imag_mask, gr),
+                                   p->grp_bits(p->yodd_mask, gr), p->tw, p->twlog, st) != 0)
+            return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+    }
     mark(p, GF_OP_ADJOINT, 2, st);
     gf::RowCombo ident{};
     ident.identity = 1;
     const double scale = kGrav / ((double)p->py * p->M);
     const gf::NyqSplit none{nullptr, 0, 0};
-    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, 0, 1, p->nz, p->ny, p->ldc, p->nz, batch, ident, none, g, p->nx,
-                           scale, p->tw, p->twlog, st) != 0)
+    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, (long)gstride, p->ngrp, p->nz, p->ny, p->ldc, p->nz, batch, ident,
+                           none, g, p->nx, scale, p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_ADJOINT, 3, st);
     return GF_OK;
@@ -628,12 +662,13 @@ gf_status gf_debug_kernel_table(const gf_plan *p, int n, double *host_out)
     const size_t field = (size_t)p->py * p->px;
     DevBuf E;
     gf_status s;
-    if ((s = hip_check(hipMalloc(&E.p, field * 6 * sizeof(double)), "debug field")) != GF_OK) return s;
-    if ((s = hip_check(hipMemset(E.p, 0, field * 6 * sizeof(double)), "memset")) != GF_OK) return s;
-    const int codes[6] = {0, 1, 2, 3, 4, 5};
-    if (gf::launch_kgen_field(E.p, 1, n, 6, codes, kgen_geom(p), make_rules(), nullptr) != 0)
+    if ((s = hip_check(hipMalloc(&E.p, field * 8 * sizeof(double)), "debug field")) != GF_OK) return s;
+    if ((s = hip_check(hipMemset(E.p, 0, field * 8 * sizeof(double)), "memset")) != GF_OK) return s;
+    const int codes[8] = {0, 1, 2, 3, 4, 5, 7, 8};
+    if (gf::launch_kgen_field(E.p, 1, n, 6, codes, kgen_geom(p), make_rules(), nullptr) != 0 ||
+        gf::launch_kgen_field((double *)E.p + 6 * field, 1, n, 2, codes + 6, kgen_geom(p), make_rules(), nullptr) != 0)
         return fail(GF_EDEVICE, "kernel table launch failed");
-    std::vector<double> h(field * 6);
+    std::vector<double> h(field * 8);
     if ((s = hip_check(hipMemcpy(h.data(), E.p, h.size() * sizeof(double), hipMemcpyDeviceToHost), "copy")) != GF_OK)
         return s;
     const int na = 2 * p->nx - 1, nb = 2 * p->ny - 1;
@@ -641,10 +676,12 @@ gf_status gf_debug_kernel_table(const gf_plan *p, int n, double *host_out)
         for (int a = -(p->nx - 1); a <= p->nx - 1; ++a) {
             const size_t src = (size_t)((b + p->py) % p->py) * p->px + (size_t)((a + p->px) % p->px);
             const size_t dst = (size_t)(b + p->ny - 1) * na + (size_t)(a + p->nx - 1);
-            double v[6];
-            for (int c = 0; c < 6; ++c) v[c] = kGrav * h[(size_t)c * field + src];
+            double v[8];
+            for (int c = 0; c < 8; ++c) v[c] = kGrav * h[(size_t)c * field + src];
             for (int c = 0; c < 6; ++c) host_out[(size_t)c * na * nb + dst] = v[c];
             host_out[(size_t)6 * na * nb + dst] = -(v[1] + v[4]);
+            host_out[(size_t)7 * na * nb + dst] = v[6];
+            host_out[(size_t)8 * na * nb + dst] = v[7];
         }
     return GF_OK;
 }
@@ -654,22 +691,23 @@ gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double 
     if (!p || !host_out) return fail(GF_EINVAL, "NULL argument");
     if (n < 0 || n >= p->nz) return fail(GF_EINVAL, "layer %d out of range", n);
     int code = -1;
-    for (int c = 0; c < 6; ++c)
-        if (component == (1u << c)) code = c;
-    const int slot = code >= 0 ? p->slot_of(code) : -1;
-    if (slot < 0) return fail(GF_EINVAL, "component 0x%x has no resident spectrum", component);
-    // layout [n][row][slot][QP], rows in the order kx = 0, Px/2, 1, ..., Px/2-1
-    const size_t layer = (size_t)p->U * p->n_spec * p->QP;
+    for (int c = 0; c < gf::kMaxOut; ++c)
+        if (c != 6 && component == (1u << c)) code = c;
+    const int slot_all = code >= 0 ? p->slot_of(code) : -1;
+    if (slot_all < 0) return fail(GF_EINVAL, "component 0x%x has no resident spectrum", component);
+    const int gr = slot_all / gf::kColMaxSpec, slot = slot_all - p->grp_c0[gr], cs = p->grp_cs[gr];
+    // group layout [n][row][slot][QP], rows in the order kx = 0, Px/2, 1, ..., Px/2-1
+    const size_t layer = (size_t)p->U * cs * p->QP;
     std::vector<double> lay(layer);
     gf_status s;
     if (p->fp64()) {
-        if ((s = hip_check(hipMemcpy(lay.data(), (const double *)p->spec + (size_t)n * layer, layer * sizeof(double),
-                                     hipMemcpyDeviceToHost), "copy")) != GF_OK)
+        if ((s = hip_check(hipMemcpy(lay.data(), (const double *)p->spec_group(gr) + (size_t)n * layer,
+                                     layer * sizeof(double), hipMemcpyDeviceToHost), "copy")) != GF_OK)
             return s;
     } else {
         std::vector<float> tmp(layer);
-        if ((s = hip_check(hipMemcpy(tmp.data(), (const float *)p->spec + (size_t)n * layer, layer * sizeof(float),
-                                     hipMemcpyDeviceToHost), "copy")) != GF_OK)
+        if ((s = hip_check(hipMemcpy(tmp.data(), (const float *)p->spec_group(gr) + (size_t)n * layer,
+                                     layer * sizeof(float), hipMemcpyDeviceToHost), "copy")) != GF_OK)
             return s;
         for (size_t i = 0; i < layer; ++i) lay[i] = tmp[i];
     }
@@ -677,7 +715,7 @@ gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double 
         const int row = kx == 0 ? 0 : (kx == p->M ? 1 : kx + 1);
         for (int ky = 0; ky < p->Q; ++ky)
             host_out[(size_t)kx * p->Q + ky] =
-                lay[((size_t)row * p->n_spec + slot) * p->QP + gf::spec_position(p->fp64(), p->py, ky)];
+                lay[((size_t)row * cs + slot) * p->QP + gf::spec_position(p->fp64(), p->py, ky)];
     }
     return GF_OK;
 }

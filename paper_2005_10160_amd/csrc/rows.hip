@@ -34,7 +34,7 @@ __device__ __forceinline__ Term<T> combo_term(const RowCombo &cmb, int o)
     Term<T> r{1, o, o, T(1), T(0)};
     if (cmb.identity) return r;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
+    for (int k = 0; k < kMaxOut; ++k)
         if (o == k) {
             r.n = cmb.nterm[k];
             r.s0 = cmb.src[k][0];
@@ -279,7 +279,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     bool two = false;   // some output combines two spectra (gzz)
     if (!cmb.identity)
 #pragma unroll
-        for (int o = 0; o < 8; ++o) two |= o < nsub && cmb.nterm[o] > 1;
+        for (int o = 0; o < kMaxOut; ++o) two |= o < nsub && cmb.nterm[o] > 1;
     const unsigned r0 = threadIdx.x % TR, u0 = threadIdx.x / TR;
     long off0, off1;
     T wa, wb;

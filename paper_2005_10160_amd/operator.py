@@ -12,10 +12,11 @@ import torch
 
 from . import _native as nat
 
-COMPONENTS = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz")
-GZ, GXX, GXY, GXZ, GYY, GYZ, GZZ = (1 << i for i in range(7))
+COMPONENTS = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz", "gx", "gy")
+GZ, GXX, GXY, GXZ, GYY, GYZ, GZZ, GX, GY = (1 << i for i in range(9))
 ALL6 = 0x3F
 ALL7 = 0x7F
+ALL9 = 0x1FF
 
 
 def components_mask(components):
@@ -64,7 +65,7 @@ class Plan:
         self.info = info
         self.nx, self.ny, self.nz = info.nx, info.ny, info.nz
         self.n_out = info.n_out
-        self.out_components = tuple(COMPONENTS[i] for i in range(7) if self.mask >> i & 1)
+        self.out_components = tuple(COMPONENTS[i] for i in range(len(COMPONENTS)) if self.mask >> i & 1)
 
     # -- lifetime ---------------------------------------------------------
     def close(self):
@@ -175,7 +176,7 @@ class Plan:
     # -- test access ---------------------------------------------------------
     def debug_kernel_table(self, n):
         import numpy as np
-        out = np.zeros((7, 2 * self.ny - 1, 2 * self.nx - 1))
+        out = np.zeros((len(COMPONENTS), 2 * self.ny - 1, 2 * self.nx - 1))
         nat.check(nat.load().gf_debug_kernel_table(self._h, int(n), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                   "gf_debug_kernel_table")
         return out

@@ -53,7 +53,7 @@ class GeometryKey:
 
     @property
     def n_out(self):
-        return bin(self.components & 0x7F).count("1")
+        return bin(self.components & 0x1FF).count("1")
 
 
 @dataclass
@@ -91,9 +91,9 @@ def _circulant(n):
 def spectra_bytes(key: GeometryKey, elem: int) -> int:
     """Resident spectra of a plan: one real per frequency of the quarter plane
     for each stored component and layer."""
-    spec = key.components & 0x3F
+    spec = key.components & 0x1BF        # every component but gzz has a spectrum
     if key.components & 0x40:
-        spec |= 0x12
+        spec |= 0x12                       # gzz = -(gxx + gyy)
     n_spec = bin(spec).count("1")
     return n_spec * key.nz * (_circulant(key.nx) // 2 + 1) * (_circulant(key.ny) // 2 + 1) * elem
 

@@ -55,7 +55,7 @@ def test_status_strings(lib):
     ((16, 16, 8, 50.0, 50.0, 50.0, 0.0, 0x3F, 0, 0), "h"),
     ((16, 16, 8, 50.0, 50.0, 50.0, float("nan"), 0x3F, 0, 0), "h nan"),
     ((16, 16, 8, 50.0, 50.0, 50.0, 25.0, 0, 0, 0), "mask"),
-    ((16, 16, 8, 50.0, 50.0, 50.0, 25.0, 0x80, 0, 0), "mask bits"),
+    ((16, 16, 8, 50.0, 50.0, 50.0, 25.0, 0x200, 0, 0), "mask bits"),
     ((16, 16, 8, 50.0, 50.0, 50.0, 25.0, 0x3F, 7, 0), "precision"),
     ((16, 16, 8, 50.0, 50.0, 50.0, 25.0, 0x3F, 0, -1), "max_batch"),
 ])

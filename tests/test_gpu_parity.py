@@ -16,7 +16,11 @@ pytestmark = pytest.mark.gpu
 
 TOL64 = 1e-10
 TOL32 = 1e-5
-NAMES = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz")
+NAMES = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz", "gx", "gy")
+NC = len(NAMES)
+ALL9 = 0x1FF
+TENSOR = (1, 2, 3, 4, 5, 6)
+VECTOR = (0, 7, 8)   # gz, gx, gy
 
 
 def note(msg):
@@ -38,7 +42,7 @@ def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
-def run_forward(gf, g, rho, mask=0x7F, prec="f64"):
+def run_forward(gf, g, rho, mask=ALL9, prec="f64"):
     dt = torch.float64 if prec == "f64" else torch.float32
     p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, prec)
     d = p.forward(torch.from_numpy(np.ascontiguousarray(rho)).to("cuda", dt))
@@ -62,7 +66,7 @@ def test_kernel_table_matches_oracle(gf, orc, geom, layers):
     for n in layers:
         got = p.debug_kernel_table(n)
         want = orc.kernel_table(geom, n, mode=1)
-        for c in range(7):
+        for c in range(NC):
             s = np.abs(want[c]).max()
             diff = np.abs(got[c] - want[c])
             assert diff.max() <= 1e-12 * s, (n, NAMES[c], diff.max() / s)
@@ -72,20 +76,23 @@ def test_kernel_table_matches_oracle(gf, orc, geom, layers):
 
 def test_resident_spectrum_is_dft_of_oracle_table(gf, orc):
     """The quarter-plane spectra equal numpy's DFT of the oracle's table placed
-    in the circulant (unit G); the other part of each spectrum is zero."""
+    in the circulant (unit G); the other part of each spectrum is zero.  The
+    plan holds eight spectra, stored in two groups."""
     g = Geometry(12, 10, 3, 20.0, 30.0, 15.0, 9.0)
-    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x3F, "f64")
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9 & ~0x40, "f64")
     px, py = p.info.px, p.info.py
     G = orc.grav_const()
     a = np.arange(-(g.nx - 1), g.nx) % px
     b = np.arange(-(g.ny - 1), g.ny) % py
     for n in range(g.nz):
         t = orc.kernel_table(g, n, mode=1) / G
-        for c, name in enumerate(NAMES[:6]):
+        for c, name in enumerate(NAMES):
+            if name == "gzz":
+                continue
             emb = np.zeros((py, px))
             emb[np.ix_(b, a)] = t[c]
             kh = np.fft.fft2(emb)            # [ky][kx]
-            imag = name in ("gxz", "gyz")
+            imag = name in ("gxz", "gyz", "gx", "gy")
             want = (kh.imag if imag else kh.real)[: py // 2 + 1, : px // 2 + 1].T
             other = (kh.real if imag else kh.imag)
             s = np.abs(kh).max()
@@ -101,7 +108,7 @@ def test_forward_tiny_fp64(gf, orc):
     rho = tiny_density(g.nx, g.ny, g.nz)
     got = run_forward(gf, g, rho)
     want = orc.forward_grid(g, rho)
-    for c in range(7):
+    for c in range(NC):
         e = rel(got[c], want[c])
         note("tiny fp64 %s rel %.2e" % (NAMES[c], e))
         assert e <= TOL64, NAMES[c]
@@ -127,15 +134,23 @@ def test_forward_ragged_and_anisotropic(gf, orc, geom):
     # With one column (nx = 1) or one row (ny = 1) every station lies on a
     # symmetry plane of every cell, where gxy and gxz (or gyz) vanish: the
     # oracle's values there are rounding noise, so tensor components are
-    # measured against the size of the whole tensor.
-    tensor = max(np.linalg.norm(want[c]) for c in range(1, 7))
-    for c in range(7):
-        ref = np.linalg.norm(want[c]) if c == 0 else max(np.linalg.norm(want[c]), 1e-6 * tensor)
+    # measured against the size of the whole tensor (gx and gy, which vanish
+    # there too, against the size of the field vector).
+    tensor = max(np.linalg.norm(want[c]) for c in TENSOR)
+    vector = max(np.linalg.norm(want[c]) for c in VECTOR)
+    for c in range(NC):
+        size = tensor if c in TENSOR else vector
+        ref = np.linalg.norm(want[c]) if c == 0 else max(np.linalg.norm(want[c]), 1e-6 * size)
         assert np.linalg.norm(got[c] - want[c]) <= TOL64 * ref, NAMES[c]
 
 
+# the last three need seven or eight spectra: two column-pass groups, the
+# second of one or two spectra
 @pytest.mark.parametrize("names", [("gz",), ("gzz",), ("gxy", "gyz"), ("gz", "gzz"), ("gxz", "gyy", "gzz"),
-                                   ("gz", "gxx", "gxy", "gxz", "gyy", "gyz")])
+                                   ("gz", "gxx", "gxy", "gxz", "gyy", "gyz"), ("gx",), ("gy",),
+                                   ("gz", "gx", "gy"), ("gyz", "gx", "gzz"),
+                                   ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gx"),
+                                   ("gxx", "gxy", "gxz", "gyy", "gyz", "gzz", "gx", "gy"), NAMES])
 def test_forward_component_subsets(gf, orc, names):
     g = Geometry(10, 14, 4, 20.0, 25.0, 15.0, 7.0)
     rho = tiny_density(g.nx, g.ny, g.nz, seed=3, block=None)
@@ -152,7 +167,7 @@ def test_forward_tiny_fp32(gf, orc):
     rho = tiny_density(g.nx, g.ny, g.nz)
     got = run_forward(gf, g, rho, prec="f32")
     want = orc.forward_grid(g, rho)
-    for c in range(7):
+    for c in range(NC):
         e = rel(got[c], want[c])
         note("tiny fp32 %s rel %.2e" % (NAMES[c], e))
         assert e <= TOL32, NAMES[c]
@@ -161,7 +176,7 @@ def test_forward_tiny_fp32(gf, orc):
 def test_batch_equals_single(gf):
     g = Geometry(24, 16, 6, 20.0, 20.0, 20.0, 10.0)
     rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (1, 2, 3)])
-    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, "f64")
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, "f64")
     both = p.forward(torch.from_numpy(rho).cuda()).cpu().numpy()
     for b in range(3):
         one = p.forward(torch.from_numpy(rho[b]).cuda()).cpu().numpy()
@@ -179,7 +194,7 @@ def test_wave_split_batches(gf, orc, nx, ny, prec, tol):
     g = Geometry(nx, ny, 37, 20.0, 25.0, 15.0, 7.0)
     dt = torch.float64 if prec == "f64" else torch.float32
     rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (4, 5, 6)])
-    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, prec)
     note("wave split %dx%dx%d %s: batch of 3" % (nx, ny, g.nz, prec))
     both = p.forward(torch.from_numpy(rho).to("cuda", dt)).double().cpu().numpy()
     for b in range(3):
@@ -187,12 +202,12 @@ def test_wave_split_batches(gf, orc, nx, ny, prec, tol):
         assert np.array_equal(both[b], one), b
     st = np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (nx // 3, (2 * ny) // 3)])
     want = orc.forward(g, rho[1], st)
-    for c in range(7):
+    for c in range(NC):
         gv = both[1][c][st[:, 1], st[:, 0]]
         e = rel(gv, want[:, c])
         assert e <= tol, (NAMES[c], e)
     rng = np.random.default_rng(nx + ny)
-    r = rng.uniform(-1.0, 1.0, size=(3, 7, ny, nx))
+    r = rng.uniform(-1.0, 1.0, size=(3, NC, ny, nx))
     gt = p.adjoint(torch.from_numpy(r).to("cuda", dt)).double().cpu().numpy()
     for b in range(3):
         one = p.adjoint(torch.from_numpy(r[b]).to("cuda", dt)).double().cpu().numpy()
@@ -220,9 +235,9 @@ def test_paper_validation_model(gf, orc):
     got = run_forward(gf, g, rho)
     st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
     want = orc.blocks_at_stations(g, [(17, 23, 17, 23, 10, 16, 300.0)], st)
-    want = want.reshape(g.ny, g.nx, 7).transpose(2, 0, 1)
+    want = want.reshape(g.ny, g.nx, NC).transpose(2, 0, 1)
     worst = 0.0
-    for c in range(7):
+    for c in range(NC):   # Fig. 6-7 include the first derivatives
         e = rel(got[c], want[c])
         worst = max(worst, e)
         note("paper model %s rel %.2e" % (NAMES[c], e))
@@ -233,22 +248,24 @@ def test_paper_validation_model(gf, orc):
 def test_adjoint_matches_oracle(gf, orc):
     g = Geometry(9, 7, 4, 30.0, 40.0, 25.0, 15.0)
     rng = np.random.default_rng(5)
-    r = rng.standard_normal((7, g.ny, g.nx))
-    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, "f64")
+    r = rng.standard_normal((NC, g.ny, g.nx))
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, "f64")
     got = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy()
-    want = orc.adjoint(g, r, 0x7F)
+    want = orc.adjoint(g, r, ALL9)
     assert rel(got, want) <= TOL64
     p.close()
 
 
-@pytest.mark.parametrize("names", [("gz",), ("gzz",), ("gxx", "gzz"), ("gxz", "gyz", "gxy")])
+@pytest.mark.parametrize("names", [("gz",), ("gzz",), ("gxx", "gzz"), ("gxz", "gyz", "gxy"), ("gx",),
+                                   ("gy", "gzz"), ("gz", "gx", "gy"),
+                                   ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gy")])
 def test_adjoint_component_subsets(gf, orc, names):
     g = Geometry(11, 6, 3, 20.0, 30.0, 10.0, 5.0)
     mask = sum(1 << NAMES.index(n) for n in names)
     order = sorted(names, key=NAMES.index)
     rng = np.random.default_rng(6)
     r_out = rng.standard_normal((len(order), g.ny, g.nx))
-    r_full = np.zeros((7, g.ny, g.nx))
+    r_full = np.zeros((NC, g.ny, g.nx))
     for i, n in enumerate(order):
         r_full[NAMES.index(n)] = r_out[i]
     p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, "f64")
@@ -264,8 +281,8 @@ def test_dot_product(gf, prec, tol):
     dt = torch.float64 if prec == "f64" else torch.float32
     gen = torch.Generator(device="cpu").manual_seed(11)
     m = torch.randn((2, g.nz, g.ny, g.nx), generator=gen, dtype=torch.float64)
-    r = torch.randn((2, 7, g.ny, g.nx), generator=gen, dtype=torch.float64)
-    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+    r = torch.randn((2, NC, g.ny, g.nx), generator=gen, dtype=torch.float64)
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, prec)
     gm = p.forward(m.to("cuda", dt)).double().cpu()
     gtr = p.adjoint(r.to("cuda", dt)).double().cpu()
     lhs = float((gm * r).sum())
@@ -287,7 +304,7 @@ def test_medium_grid_sampled_fp64(gf, orc):
     st = sample_stations(g.nx, g.ny, 7, seed=204)
     note("medium grid: oracle at %d stations" % len(st))
     want = orc.forward(g, rho, st)
-    for c in range(7):
+    for c in range(NC):
         gv = got[c][st[:, 1], st[:, 0]]
         e = rel(gv, want[:, c])
         note("medium fp64 %s sampled rel %.2e" % (NAMES[c], e))
@@ -304,11 +321,11 @@ def test_paper_scale_sampled(gf, orc, prec, tol):
     note("paper scale %s: density" % prec)
     rho = prisms_and_grf(g.nx, g.ny, g.nz, 20, 302, 303)
     note("paper scale %s: forward" % prec)
-    got = run_forward(gf, g, rho, mask=0x7F, prec=prec)
+    got = run_forward(gf, g, rho, mask=ALL9, prec=prec)
     st = sample_stations(g.nx, g.ny, 0, seed=1)[[8, 0, 3]]
     note("paper scale %s: oracle at %d stations" % (prec, len(st)))
     want = orc.forward(g, rho, st)
-    for c in range(7):
+    for c in range(NC):
         gv = got[c][st[:, 1], st[:, 0]]
         e = rel(gv, want[:, c])
         note("paper scale %s %s sampled rel %.2e" % (prec, NAMES[c], e))
@@ -327,7 +344,7 @@ SWEEP = [(9, 5), (5, 9), (33, 17), (17, 33), (129, 65), (65, 129), (513, 257), (
 def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
     """Forward and adjoint at every row and column transform length against
     the direct sum at sampled stations (corners, centre, an off-centre
-    station; nz = 3, all seven components).  The FP64 column pass of length
+    station; nz = 3, all nine components).  The FP64 column pass of length
     4096 does not fit in LDS: its plan must fail with GF_EUNSUPPORTED."""
     from paper_2005_10160_amd import _native
     g = Geometry(nx, ny, 3, 20.0, 25.0, 15.0, 7.0)
@@ -338,29 +355,29 @@ def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
         py *= 2
     if prec == "f64" and py > 2048:
         with pytest.raises(_native.GravFFTError) as ei:
-            gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+            gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, prec)
         assert ei.value.status == _native.GF_EUNSUPPORTED
         return
     note("sweep %dx%d %s: forward" % (nx, ny, prec))
-    got = run_forward(gf, g, rho, mask=0x7F, prec=prec)
+    got = run_forward(gf, g, rho, mask=ALL9, prec=prec)
     st = np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (nx // 3, (2 * ny) // 3), (nx - 1, 0)])
     want = orc.forward(g, rho, st)
-    scale = np.linalg.norm(want[:, :6])
-    for c in range(7):
+    for c in range(NC):
         gv = got[c][st[:, 1], st[:, 0]]
         # components that vanish on a symmetry line of a thin grid are
-        # compared against the whole tensor's size
+        # compared against the size of the whole tensor (or field vector)
+        scale = np.linalg.norm(want[:, list(TENSOR if c in TENSOR else VECTOR)])
         e = float(np.linalg.norm(gv - want[:, c]) / max(np.linalg.norm(want[:, c]), 1e-3 * scale))
         assert e <= tol, (NAMES[c], e)
     # adjoint of a random residual at sampled cells
     dt = torch.float64 if prec == "f64" else torch.float32
-    r = rng.uniform(-1.0, 1.0, size=(7, ny, nx))
-    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x7F, prec)
+    r = rng.uniform(-1.0, 1.0, size=(NC, ny, nx))
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, prec)
     gt = p.adjoint(torch.from_numpy(r).to("cuda", dt)).double().cpu().numpy()
     torch.cuda.synchronize()
     p.close()
     cells = np.array([(0, 0, 0), (nx - 1, ny - 1, g.nz - 1), (nx // 2, ny // 3, 1)])
-    wa = orc.adjoint(g, r, 0x7F, cells)
+    wa = orc.adjoint(g, r, ALL9, cells)
     ga = gt[cells[:, 2], cells[:, 1], cells[:, 0]]
     e = rel(ga, wa)
     note("sweep %dx%d %s: adjoint rel %.2e" % (nx, ny, prec, e))
