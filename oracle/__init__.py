@@ -67,6 +67,14 @@ def _load():
         lib.orc_dense_matrix.restype = i
         lib.orc_blocks_at_stations.argtypes = [i, i, i, d, d, d, d, i, pi, pd, i, pi, pi, pd]
         lib.orc_blocks_at_stations.restype = i
+        lib.orc_offset_kernels_z.argtypes = [d, d, d, pd, d, i, i, pi, pi, i, pd]
+        lib.orc_offset_kernels_z.restype = i
+        lib.orc_forward_z.argtypes = [i, i, i, d, d, d, pd, d, i, pd, i, pi, pi, pd]
+        lib.orc_forward_z.restype = i
+        lib.orc_adjoint_z.argtypes = [i, i, i, d, d, d, pd, d, i, u, pd, i, pi, pi, pi, pd]
+        lib.orc_adjoint_z.restype = i
+        lib.orc_blocks_at_stations_z.argtypes = [i, i, i, d, d, d, pd, d, i, pi, pd, i, pi, pi, pd]
+        lib.orc_blocks_at_stations_z.restype = i
         lib.orc_max_threads.restype = i
         lib.orc_set_threads.argtypes = [i]
         lib.orc_grav_const.restype = d
@@ -84,6 +92,23 @@ def _pi(a):
 
 def _geom(g):
     return (int(g.nx), int(g.ny), int(g.nz), float(g.dx), float(g.dy), float(g.dz), float(g.h))
+
+
+def _edges(geom, zedges):
+    """Layer edges as a contiguous float64 array of nz + 1 depths (layer n
+    spans [zedges[n], zedges[n+1]] below the top), or None for uniform
+    layers of thickness geom.dz."""
+    if zedges is None:
+        return None
+    z = np.ascontiguousarray(zedges, dtype=np.float64).ravel()
+    if z.size != geom.nz + 1:
+        raise ValueError("zedges must hold nz + 1 depths")
+    return z
+
+
+def _geom_z(g, z):
+    nx, ny, nz, dx, dy, dz, h = _geom(g)
+    return (nx, ny, nz, dx, dy, dz, _pd(z), h)
 
 
 def grav_const():
@@ -124,7 +149,7 @@ def gl_rule(order):
     return x, w
 
 
-def offset_kernels(geom, n, a, b, mode=0):
+def offset_kernels(geom, n, a, b, mode=0, zedges=None):
     """Kernel of the cell at offset (a, b) = (l-p, m-q) in layer n relative to
     its station (translation equivalence, eq. 7/10).  mode 0: closed form;
     mode 1: closed form near, 8^3 Gauss-Legendre beyond 24 half-diagonals.
@@ -133,24 +158,31 @@ def offset_kernels(geom, n, a, b, mode=0):
     b = np.ascontiguousarray(b, dtype=np.int32).ravel()
     assert a.shape == b.shape
     out = np.zeros((a.size, NCOMP))
-    rc = _load().orc_offset_kernels(float(geom.dx), float(geom.dy), float(geom.dz), float(geom.h),
-                                    int(n), int(a.size), _pi(a), _pi(b), int(mode), _pd(out))
+    z = _edges(geom, zedges)
+    if z is not None:
+        rc = _load().orc_offset_kernels_z(float(geom.dx), float(geom.dy), float(geom.dz), _pd(z), float(geom.h),
+                                          int(n), int(a.size), _pi(a), _pi(b), int(mode), _pd(out))
+    else:
+        rc = _load().orc_offset_kernels(float(geom.dx), float(geom.dy), float(geom.dz), float(geom.h),
+                                        int(n), int(a.size), _pi(a), _pi(b), int(mode), _pd(out))
     if rc != 0:
         raise ValueError("bad geometry")
     return out
 
 
-def kernel_table(geom, n, mode=0):
+def kernel_table(geom, n, mode=0, zedges=None):
     """Full offset table of layer n: (NCOMP, 2ny-1, 2nx-1), index [c][b+ny-1][a+nx-1]."""
     aa, bb = np.meshgrid(np.arange(-(geom.nx - 1), geom.nx), np.arange(-(geom.ny - 1), geom.ny))
-    k = offset_kernels(geom, n, aa.ravel(), bb.ravel(), mode)
+    k = offset_kernels(geom, n, aa.ravel(), bb.ravel(), mode, zedges)
     return k.T.reshape(NCOMP, 2 * geom.ny - 1, 2 * geom.nx - 1)
 
 
-def forward(geom, rho, stations=None):
+def forward(geom, rho, stations=None, zedges=None):
     """Direct sum d = G rho (eq. 3) at stations (array of (p, q)); all
     stations in row order (q major) when None.  rho: (nz,ny,nx) or
-    (nb,nz,ny,nx) in kg/m^3.  Returns (nb, nst, NCOMP) (nb dropped for 3-D rho)."""
+    (nb,nz,ny,nx) in kg/m^3.  zedges: nz + 1 layer-edge depths of a layered
+    mesh (None: uniform layers of geom.dz).  Returns (nb, nst, NCOMP) (nb
+    dropped for 3-D rho)."""
     rho = np.asarray(rho, dtype=np.float64)
     squeeze = rho.ndim == 3
     if squeeze:
@@ -165,16 +197,20 @@ def forward(geom, rho, stations=None):
     sp = np.ascontiguousarray(st[:, 0])
     sq = np.ascontiguousarray(st[:, 1])
     out = np.zeros((nb, st.shape[0], NCOMP))
-    rc = _load().orc_forward(*_geom(geom), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
+    z = _edges(geom, zedges)
+    if z is not None:
+        rc = _load().orc_forward_z(*_geom_z(geom, z), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
+    else:
+        rc = _load().orc_forward(*_geom(geom), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
     if rc != 0:
         raise ValueError("oracle forward failed (%d)" % rc)
     return out[0] if squeeze else out
 
 
-def forward_grid(geom, rho):
+def forward_grid(geom, rho, zedges=None):
     """Direct sum at every station: (nb, NCOMP, ny, nx) (nb dropped for 3-D rho)."""
     squeeze = np.asarray(rho).ndim == 3
-    out = forward(geom, rho)
+    out = forward(geom, rho, zedges=zedges)
     if squeeze:
         out = out[None]
     nb = out.shape[0]
@@ -182,7 +218,7 @@ def forward_grid(geom, rho):
     return res[0] if squeeze else res
 
 
-def adjoint(geom, r, mask, cells=None):
+def adjoint(geom, r, mask, cells=None, zedges=None):
     """Direct adjoint g(l,m,n) = sum_c sum_{p,q} G_c[(p,q),(l,m,n)] r_c(p,q).
     r: (NCOMP, ny, nx) or (nb, NCOMP, ny, nx) indexed by component slot; only slots in
     ``mask`` (bit c = component c) are read.  cells: array of (l, m, n);
@@ -201,8 +237,13 @@ def adjoint(geom, r, mask, cells=None):
     cells = np.ascontiguousarray(cells, dtype=np.int32).reshape(-1, 3)
     cl, cm, cn = (np.ascontiguousarray(cells[:, i]) for i in range(3))
     out = np.zeros((nb, cells.shape[0]))
-    rc = _load().orc_adjoint(*_geom(geom), nb, ctypes.c_uint(int(mask)), _pd(r), int(cells.shape[0]),
-                             _pi(cl), _pi(cm), _pi(cn), _pd(out))
+    z = _edges(geom, zedges)
+    if z is not None:
+        rc = _load().orc_adjoint_z(*_geom_z(geom, z), nb, ctypes.c_uint(int(mask)), _pd(r), int(cells.shape[0]),
+                                   _pi(cl), _pi(cm), _pi(cn), _pd(out))
+    else:
+        rc = _load().orc_adjoint(*_geom(geom), nb, ctypes.c_uint(int(mask)), _pd(r), int(cells.shape[0]),
+                                 _pi(cl), _pi(cm), _pi(cn), _pd(out))
     if rc != 0:
         raise ValueError("oracle adjoint failed (%d)" % rc)
     if full:
@@ -220,7 +261,7 @@ def dense_matrix(geom, comp):
     return out
 
 
-def blocks_at_stations(geom, blocks, stations):
+def blocks_at_stations(geom, blocks, stations, zedges=None):
     """Superposition of uniform blocks, each integrated as one merged prism.
     blocks: iterable of (l0, l1, m0, m1, n0, n1, rho).  Returns (nst, NCOMP)."""
     blocks = list(blocks)
@@ -230,8 +271,13 @@ def blocks_at_stations(geom, blocks, stations):
     sp = np.ascontiguousarray(st[:, 0])
     sq = np.ascontiguousarray(st[:, 1])
     out = np.zeros((st.shape[0], NCOMP))
-    rc = _load().orc_blocks_at_stations(*_geom(geom), len(blocks), _pi(blk), _pd(val), int(st.shape[0]),
-                                        _pi(sp), _pi(sq), _pd(out))
+    z = _edges(geom, zedges)
+    if z is not None:
+        rc = _load().orc_blocks_at_stations_z(*_geom_z(geom, z), len(blocks), _pi(blk), _pd(val),
+                                              int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
+    else:
+        rc = _load().orc_blocks_at_stations(*_geom(geom), len(blocks), _pi(blk), _pd(val), int(st.shape[0]),
+                                            _pi(sp), _pi(sq), _pd(out))
     if rc != 0:
         raise ValueError("bad blocks")
     return out

@@ -22,6 +22,11 @@
  *   - Cell (l,m,n) spans x in [l dx,(l+1)dx], y in [m dy,(m+1)dy],
  *     z in [n dz,(n+1)dz]; station (p,q) sits at ((p+1/2)dx, (q+1/2)dy, -h),
  *     one above each surface cell (section 2.1: N_d = nx*ny).
+ *   - Layered meshes (the *_z entry points): layer n spans depths
+ *     [zedge[n], zedge[n+1]] instead, for a strictly increasing zedge[nz+1]
+ *     with zedge[0] >= 0.  The paper takes the layers uniform (section 2.1);
+ *     translation equivalence (eq. 7) holds within each layer whatever its
+ *     thickness, so each layer keeps its own BTTB block.
  *   - Relative coordinates are source minus station, so z > 0 inside cells.
  *   - U = G rho \iiint dV / r;  g = grad U (pointing at the mass, gz > 0 for
  *     a positive mass below);  T_ab = d^2 U / da db.
@@ -278,16 +283,34 @@ int orc_gl_rule(int order, double *x, double *w)
 /* Kernel by offset (translation equivalence, eq. 7 / eq. 10).               */
 /* ------------------------------------------------------------------------ */
 
+/* Depth of the top of layer n (n = nz: the bottom of the model). */
+static ld layer_depth(int n, double dz, const double *zedge)
+{
+    return zedge ? (ld)zedge[n] : (ld)n * dz;
+}
+
+/* 0 when zedge is NULL or a strictly increasing list of nz+1 finite depths
+ * starting at >= 0. */
+static int check_edges(int nz, const double *zedge)
+{
+    if (!zedge) return 0;
+    if (!(zedge[0] >= 0) || !isfinite(zedge[0])) return -1;
+    for (int n = 0; n < nz; ++n)
+        if (!(zedge[n + 1] > zedge[n]) || !isfinite(zedge[n + 1])) return -1;
+    return 0;
+}
+
 /* Bounds of the cell at offset (a, b) = (l - p, m - q) in layer n, relative
  * to its station. */
-static void cell_bounds(int a, int b, int n, double dx, double dy, double dz, double h, ld bx[6])
+static void cell_bounds(int a, int b, int n, double dx, double dy, double dz, const double *zedge,
+                        double h, ld bx[6])
 {
     bx[0] = ((ld)a - 0.5L) * dx;
     bx[1] = ((ld)a + 0.5L) * dx;
     bx[2] = ((ld)b - 0.5L) * dy;
     bx[3] = ((ld)b + 0.5L) * dy;
-    bx[4] = (ld)h + (ld)n * dz;
-    bx[5] = (ld)h + (ld)(n + 1) * dz;
+    bx[4] = (ld)h + layer_depth(n, dz, zedge);
+    bx[5] = (ld)h + layer_depth(n + 1, dz, zedge);
 }
 
 /* Public: kernel values of cells given by offsets (a[i], b[i]) in layer n.
@@ -297,17 +320,19 @@ static void cell_bounds(int a, int b, int n, double dx, double dy, double dz, do
  *         (at that distance its truncation error is far below long-double
  *         rounding, while the closed form starts to lose digits).
  * out[count][9]. */
-int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int count, const int *a,
-                       const int *b, int mode, double *out)
+int orc_offset_kernels_z(double dx, double dy, double dz, const double *zedge, double h, int n, int count,
+                         const int *a, const int *b, int mode, double *out)
 {
-    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0) || n < 0 || count < 0) return -1;
+    if (!(dx > 0 && dy > 0 && (zedge || dz > 0) && h > 0) || n < 0 || count < 0) return -1;
+    if (zedge && check_edges(n + 1, zedge) != 0) return -1;
     ld gx[GL_MAX], gw[GL_MAX];
     gl_rule(8, gx, gw);
-    ld hd = sqrtl((ld)dx * dx + (ld)dy * dy + (ld)dz * dz) / 2;
+    ld tz = layer_depth(n + 1, dz, zedge) - layer_depth(n, dz, zedge);
+    ld hd = sqrtl((ld)dx * dx + (ld)dy * dy + tz * tz) / 2;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int i = 0; i < count; ++i) {
         ld bx[6], o[NCOMP];
-        cell_bounds(a[i], b[i], n, dx, dy, dz, h, bx);
+        cell_bounds(a[i], b[i], n, dx, dy, dz, zedge, h, bx);
         ld cx = (bx[0] + bx[1]) / 2, cy = (bx[2] + bx[3]) / 2, cz = (bx[4] + bx[5]) / 2;
         ld dist = sqrtl(cx * cx + cy * cy + cz * cz);
         if (mode == 1 && dist >= 24 * hd) {
@@ -319,6 +344,12 @@ int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int cou
         for (int c = 0; c < NCOMP; ++c) out[(size_t)i * NCOMP + c] = (double)o[c];
     }
     return 0;
+}
+
+int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int count, const int *a,
+                       const int *b, int mode, double *out)
+{
+    return orc_offset_kernels_z(dx, dy, dz, NULL, h, n, count, a, b, mode, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -365,11 +396,11 @@ static inline void cell_from_planes(const ld *lo, const ld *hi, int nxn, int ix,
  * plane is evaluated once per chunk; partial sums are kept per layer and
  * reduced in layer order, so the result does not depend on the thread count
  * or the chunking. */
-int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
-                const double *rho, int nst, const int *sp, const int *sq, double *out)
+int orc_forward_z(int nx, int ny, int nz, double dx, double dy, double dz, const double *zedge, double h,
+                  int nb, const double *rho, int nst, const int *sp, const int *sq, double *out)
 {
     if (nx < 1 || ny < 1 || nz < 1 || nb < 1 || nst < 0) return -1;
-    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    if (!(dx > 0 && dy > 0 && (zedge || dz > 0) && h > 0) || check_edges(nz, zedge) != 0) return -1;
     for (int s = 0; s < nst; ++s)
         if (sp[s] < 0 || sp[s] >= nx || sq[s] < 0 || sq[s] >= ny) return -1;
     size_t nxn = (size_t)nx + 1, nyn = (size_t)ny + 1;
@@ -400,9 +431,9 @@ int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double 
             int p = sp[s], q = sq[s];
             int n0 = ch * clen, n1 = n0 + clen < nz ? n0 + clen : nz;
             /* offsets a = l - p, l in [0,nx): x nodes (a - 1/2) dx for a in [-p, nx - p]. */
-            fill_plane(lo, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)n0 * dz);
+            fill_plane(lo, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + layer_depth(n0, dz, zedge));
             for (int n = n0; n < n1; ++n) {
-                fill_plane(hi, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + (ld)(n + 1) * dz);
+                fill_plane(hi, -p, (int)nxn, -q, (int)nyn, dx, dy, (ld)h + layer_depth(n + 1, dz, zedge));
                 ld *dst = part + ((size_t)s * nz + n) * nb * NCOMP;
                 for (int m = 0; m < ny; ++m)
                     for (int l = 0; l < nx; ++l) {
@@ -436,18 +467,24 @@ int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double 
     return 0;
 }
 
+int orc_forward(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
+                const double *rho, int nst, const int *sp, const int *sq, double *out)
+{
+    return orc_forward_z(nx, ny, nz, dx, dy, dz, NULL, h, nb, rho, nst, sp, sq, out);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Direct adjoint sum: g(l,m,n) = sum_c sum_{p,q} G_c[(p,q),(l,m,n)] r_c(p,q) */
 /* ------------------------------------------------------------------------ */
 
 /* r[nb][NCOMP][ny][nx] indexed by component slot (unused slots may hold anything,
  * only comps in mask are read).  Cells (cl, cm, cn).  out[nb][ncell]. */
-int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
-                unsigned mask, const double *r, int ncell, const int *cl, const int *cm,
-                const int *cn, double *out)
+int orc_adjoint_z(int nx, int ny, int nz, double dx, double dy, double dz, const double *zedge, double h,
+                  int nb, unsigned mask, const double *r, int ncell, const int *cl, const int *cm,
+                  const int *cn, double *out)
 {
     if (nx < 1 || ny < 1 || nz < 1 || nb < 1 || ncell < 0) return -1;
-    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    if (!(dx > 0 && dy > 0 && (zedge || dz > 0) && h > 0) || check_edges(nz, zedge) != 0) return -1;
     for (int i = 0; i < ncell; ++i)
         if (cl[i] < 0 || cl[i] >= nx || cm[i] < 0 || cm[i] >= ny || cn[i] < 0 || cn[i] >= nz)
             return -1;
@@ -468,8 +505,8 @@ int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, double 
             int l = cl[i], m = cm[i], n = cn[i];
             /* a = l - p for p in [0,nx): a in [l-nx+1, l]; x nodes v in [l-nx+1, l+1]. */
             int v0 = l - nx + 1, w0 = m - ny + 1;
-            fill_plane(lo, v0, (int)nxn, w0, (int)nyn, dx, dy, (ld)h + (ld)n * dz);
-            fill_plane(hi, v0, (int)nxn, w0, (int)nyn, dx, dy, (ld)h + (ld)(n + 1) * dz);
+            fill_plane(lo, v0, (int)nxn, w0, (int)nyn, dx, dy, (ld)h + layer_depth(n, dz, zedge));
+            fill_plane(hi, v0, (int)nxn, w0, (int)nyn, dx, dy, (ld)h + layer_depth(n + 1, dz, zedge));
             for (int b = 0; b < nb; ++b) {
                 ld acc = 0;
                 for (int q = 0; q < ny; ++q)
@@ -487,6 +524,13 @@ int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, double 
         free(hi);
     }
     return err;
+}
+
+int orc_adjoint(int nx, int ny, int nz, double dx, double dy, double dz, double h, int nb,
+                unsigned mask, const double *r, int ncell, const int *cl, const int *cm,
+                const int *cn, double *out)
+{
+    return orc_adjoint_z(nx, ny, nz, dx, dy, dz, NULL, h, nb, mask, r, ncell, cl, cm, cn, out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -525,12 +569,12 @@ int orc_dense_matrix(int nx, int ny, int nz, double dx, double dy, double dz, do
  * n in [blk[6k+4],blk[6k+5]) with density val[k].  Since the closed form
  * integrates any box, a block needs one evaluation per station instead of one
  * per cell.  out[nst][NCOMP] = sum_k val[k] * K(block k). */
-int orc_blocks_at_stations(int nx, int ny, int nz, double dx, double dy, double dz, double h,
-                           int nblk, const int *blk, const double *val, int nst, const int *sp,
-                           const int *sq, double *out)
+int orc_blocks_at_stations_z(int nx, int ny, int nz, double dx, double dy, double dz, const double *zedge,
+                             double h, int nblk, const int *blk, const double *val, int nst, const int *sp,
+                             const int *sq, double *out)
 {
     if (nx < 1 || ny < 1 || nz < 1 || nblk < 0 || nst < 0) return -1;
-    if (!(dx > 0 && dy > 0 && dz > 0 && h > 0)) return -1;
+    if (!(dx > 0 && dy > 0 && (zedge || dz > 0) && h > 0) || check_edges(nz, zedge) != 0) return -1;
     for (int k = 0; k < nblk; ++k) {
         const int *B = blk + 6 * k;
         if (B[0] < 0 || B[1] > nx || B[0] >= B[1] || B[2] < 0 || B[3] > ny || B[2] >= B[3] ||
@@ -545,10 +589,17 @@ int orc_blocks_at_stations(int nx, int ny, int nz, double dx, double dy, double 
             const int *B = blk + 6 * k;
             ld o[NCOMP];
             prism_ld((ld)B[0] * dx - sx, (ld)B[1] * dx - sx, (ld)B[2] * dy - sy, (ld)B[3] * dy - sy,
-                     (ld)B[4] * dz - sz, (ld)B[5] * dz - sz, o);
+                     layer_depth(B[4], dz, zedge) - sz, layer_depth(B[5], dz, zedge) - sz, o);
             for (int c = 0; c < NCOMP; ++c) acc[c] += (ld)val[k] * o[c];
         }
         for (int c = 0; c < NCOMP; ++c) out[(size_t)s * NCOMP + c] = (double)acc[c];
     }
     return 0;
+}
+
+int orc_blocks_at_stations(int nx, int ny, int nz, double dx, double dy, double dz, double h,
+                           int nblk, const int *blk, const double *val, int nst, const int *sp,
+                           const int *sq, double *out)
+{
+    return orc_blocks_at_stations_z(nx, ny, nz, dx, dy, dz, NULL, h, nblk, blk, val, nst, sp, sq, out);
 }

@@ -355,3 +355,60 @@ def test_paper_validation_model(orc):
     direct = orc.forward(g, rho, some)
     for i, (p, q) in enumerate(some):
         assert np.allclose(direct[i], merged[:, q, p], rtol=1e-12, atol=1e-12 * np.abs(merged).max())
+
+
+# --------------------------------------------------------------- pin 13 ----
+def test_layered_mesh_merges_uniform_layers(orc):
+    """Layers of unequal thickness (a depth-stretched mesh): a layer spanning
+    two uniform layers acts as both of them with the same density
+    (superposition, eq. 3), forward and adjoint.  The merged layer's closed
+    form uses other corners than the two thin layers', so this checks the
+    layered path against the pinned uniform one."""
+    g5 = Geometry(9, 7, 5, 30.0, 40.0, 15.0, 12.0)
+    thick = [2, 1, 2]                              # uniform layers per merged layer
+    edges = np.concatenate([[0.0], np.cumsum(thick) * g5.dz])
+    g3 = Geometry(g5.nx, g5.ny, 3, g5.dx, g5.dy, 99.0, g5.h)   # dz unused with edges
+    rho3 = tiny_density(g3.nx, g3.ny, 3, seed=31, block=None)
+    rho5 = np.repeat(rho3, thick, axis=0)
+    got = orc.forward_grid(g3, rho3, zedges=edges)
+    want = orc.forward_grid(g5, rho5)
+    for c in range(orc.NCOMP):
+        assert rel(got[c], want[c]) <= 1e-13, c
+    rng = np.random.default_rng(32)
+    r = rng.standard_normal((orc.NCOMP, g5.ny, g5.nx))
+    a3 = orc.adjoint(g3, r, 0x1FF, zedges=edges)
+    a5 = orc.adjoint(g5, r, 0x1FF)
+    merged = np.add.reduceat(a5, np.concatenate([[0], np.cumsum(thick)[:-1]]), axis=0)
+    assert rel(a3, merged) <= 1e-13
+
+
+def test_layered_mesh_buried_top_and_blocks(orc):
+    """A mesh whose top lies at depth z0 below the surface equals the uniform
+    mesh seen from stations z0 higher; a stretched mesh's cells sum to the
+    merged prisms of its blocks; bad edge lists are refused."""
+    g = Geometry(8, 6, 4, 25.0, 20.0, 10.0, 6.0)
+    z0 = 37.0
+    edges = z0 + g.dz * np.arange(g.nz + 1)
+    rho = tiny_density(g.nx, g.ny, g.nz, seed=33, block=None)
+    got = orc.forward_grid(g, rho, zedges=edges)
+    high = Geometry(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + z0)
+    want = orc.forward_grid(high, rho)
+    for c in range(orc.NCOMP):
+        assert rel(got[c], want[c]) <= 1e-13, c
+
+    gs = Geometry(14, 11, 6, 25.0, 30.0, 1.0, 12.0)
+    es = np.concatenate([[0.0], np.cumsum(8.0 * 1.3 ** np.arange(6))])
+    blocks = [(2, 9, 3, 8, 1, 4, 800.0), (10, 14, 0, 5, 3, 6, -350.0), (0, 14, 0, 11, 0, 1, 120.0)]
+    rho = np.zeros((gs.nz, gs.ny, gs.nx))
+    for (l0, l1, m0, m1, n0, n1, v) in blocks:
+        rho[n0:n1, m0:m1, l0:l1] += v
+    st = np.array([(p, q) for q in range(gs.ny) for p in range(gs.nx)])
+    want = orc.blocks_at_stations(gs, blocks, st, zedges=es)
+    got = orc.forward(gs, rho, st, zedges=es)
+    for c in range(orc.NCOMP):
+        assert rel(got[:, c], want[:, c]) <= 1e-12, c
+
+    for bad in ([0.0, 10.0, 10.0, 30.0, 40.0], [-1.0, 10.0, 20.0, 30.0, 40.0],
+                [0.0, 10.0, np.nan, 30.0, 40.0]):
+        with pytest.raises(ValueError):
+            orc.forward_grid(g, rho[:4, :6, :8], zedges=bad)
