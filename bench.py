@@ -13,7 +13,9 @@ the number of kernel-matrix entries the operator applies per second
 
 One JSON line is printed.  Besides the headline FP64 forward it carries the
 FP32 path, the adjoint, a live roofline of the dominant kernel (the column
-pass), the batched inversion-step workload (512^2 x 128, 32 models, forward
+pass), the same model with other component sets (gz with the first
+derivatives gx, gy; all nine outputs) and on a depth-stretched layered mesh,
+the batched inversion-step workload (512^2 x 128, 32 models, forward
 and adjoint in both precisions), the CPU oracle timed on a bounded sample,
 and a served-latency run:
 a seeded Poisson trace of mixed requests (3 s at 200 req/s by default)
@@ -223,6 +225,7 @@ def main():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-model inversion-step timing")
+    ap.add_argument("--no-sets", action="store_true", help="skip the gz/gx/gy and nine-component timings")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the replayed request trace (0: no serving run)")
     ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
@@ -246,15 +249,18 @@ def main():
     log("bench: generating density %dx%dx%d" % (g.nx, g.ny, g.nz))
     rho_np = prisms_and_grf(g.nx, g.ny, g.nz, 20 if not args.small else 6, 302, 303)
 
-    def run(prec, steps, warmup, with_adjoint):
+    def run(prec, steps, warmup, with_adjoint, mask=gf.ALL6, zedges=None):
         dt = torch.float64 if prec == "f64" else torch.float32
-        log("bench: plan %s" % prec)
+        log("bench: plan %s, components 0x%x%s" % (prec, mask, "" if zedges is None else ", layered"))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, gf.ALL6, prec, device=dev)
+        if zedges is None:
+            p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, prec, device=dev)
+        else:
+            p = gf.plan_layered(g.nx, g.ny, g.dx, g.dy, zedges, g.h, mask, prec, device=dev)
         plan_wall = (time.perf_counter() - t0) * 1e3
         rho = torch.from_numpy(rho_np).to(dev, dt)
-        d = torch.empty((1, 6, g.ny, g.nx), dtype=dt, device=dev)
+        d = torch.empty((1, p.n_out, g.ny, g.nx), dtype=dt, device=dev)
         wsb = max(p.workspace_bytes("forward", 1), p.workspace_bytes("adjoint", 1))
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
         log("bench: timing %s forward" % prec)
@@ -348,6 +354,30 @@ def main():
                        "colpass_GBs": round(a32 / (c32 * 1e-3) / 1e9, 1), "plan_ms": round(r32["plan_ms"], 1)}
         r32["plan"].close()
         del r32
+
+    if not args.no_sets:
+        # other component sets on the same model: the first derivatives with
+        # gz, and all nine outputs (eight resident spectra, two column-pass
+        # launches of six and two); and the six components on a layered mesh
+        # (layers thickening from 5 m by 3 % per layer, 2.4 km deep)
+        stretched = [0.0] + list(np.cumsum(5.0 * 1.03 ** np.arange(g.nz)))
+        sets = {}
+        for name, mask, ze in (("gz_gx_gy", gf.GZ | gf.GX | gf.GY, None), ("all9", gf.ALL9, None),
+                               ("layered_all6", gf.ALL6, stretched)):
+            sets[name] = {}
+            for prec in ("f64", "f32"):
+                r = run(prec, 10, 2, True, mask, ze)
+                ms = sum(r["per"]) / len(r["per"])
+                nout = r["plan"].n_out
+                sets[name][prec] = {"components": nout, "ms_per_step": round(ms, 4),
+                                    "effective_evals_per_s": nout * g.nd * g.nm / (ms * 1e-3),
+                                    "pass_ms": [round(float(x), 4) for x in r["passes"].mean(axis=0)],
+                                    "adjoint_ms": round(r["adjoint_ms"], 4),
+                                    "plan_ms": round(r["plan_ms"], 1),
+                                    "spectra_bytes": r["spectra_bytes"]}
+                r["plan"].close()
+                del r
+        line["component_sets"] = sets
 
     if not args.no_batched and not args.small:
         line["batched"] = batched_step(5, 1)

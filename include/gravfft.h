@@ -131,6 +131,22 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
                          unsigned components, int precision, int max_batch, void *hip_stream,
                          gf_plan **out);
 
+/*
+ * The same for a layered (depth-stretched) mesh: layer n spans depths
+ * [z_edges[n], z_edges[n+1]] below the top instead of [n dz, (n+1) dz].  The
+ * paper takes the layers uniform (section 2.1); translation equivalence
+ * (eq. 7) holds within each layer whatever its thickness, so every layer
+ * keeps its own BTTB block and resident spectrum and the forward and adjoint
+ * calls are unchanged.
+ *   z_edges  host, nz + 1 finite depths in metres, z_edges[0] >= 0 and
+ *            strictly increasing (else GF_EINVAL); copied, the caller keeps
+ *            ownership
+ * Other arguments as gf_plan_create.
+ */
+gf_status gf_plan_create_layered(int nx, int ny, int nz, double dx, double dy, const double *z_edges, double h,
+                                 unsigned components, int precision, int max_batch, void *hip_stream,
+                                 gf_plan **out);
+
 /* Free a plan and its device memory.  NULL is accepted.  The caller must have
  * finished every call that uses the plan. */
 gf_status gf_plan_destroy(gf_plan *plan);

@@ -29,10 +29,11 @@ from .operator import (
     components_mask,
     forward,
     plan,
+    plan_layered,
 )
 
 __all__ = [
     "ALL6", "ALL7", "ALL9", "COMPONENTS", "GZ", "GXX", "GXY", "GXZ", "GYY", "GYZ", "GZZ", "GX", "GY",
     "GravityForward", "GravityOperator", "Plan", "adjoint", "components_mask",
-    "forward", "plan",
+    "forward", "plan", "plan_layered",
 ]

@@ -38,7 +38,8 @@ struct GLRules {
 
 struct KgenGeom {
     int nx, ny, px, py;
-    double dx, dy, dz, h;
+    double dx, dy, h;
+    const double *zedge;  // device, nz + 1 layer-edge depths: layer n spans [zedge[n], zedge[n+1]]
     double t_analytic;   // closed form below this many half-diagonals
     double t_gl6;        // 6^3 rule below this, 4^3 below t_gl4, 3^3 beyond
     double t_gl4;

@@ -4,7 +4,9 @@
 // (a,b) = (l-p, m-q) in layer n (translation equivalence, eq. 7 / eq. 10),
 // per unit density and with unit gravitational constant.  Relative to its
 // station the prism spans x in [(a-1/2)dx, (a+1/2)dx], y likewise,
-// z in [h + n dz, h + (n+1) dz] (z down).
+// z in [h + z_n, h + z_{n+1}] (z down), z_n the depth of the top of layer n:
+// n dz for the paper's uniform layers, any increasing list for a layered
+// (depth-stretched) mesh, each layer keeping its own BTTB block.
 //
 // Near the station the closed forms of the prism integral are used (eq. 2 for
 // gz; the tensor forms follow by integrating (3 x_a x_b - r^2 delta_ab)/r^5;
@@ -132,9 +134,9 @@ __global__ void __launch_bounds__(256)
 
     const double x1 = (a - 0.5) * g.dx, x2 = (a + 0.5) * g.dx;
     const double y1 = (b - 0.5) * g.dy, y2 = (b + 0.5) * g.dy;
-    const double z1 = g.h + n * g.dz, z2 = g.h + (n + 1) * g.dz;
+    const double z1 = g.h + g.zedge[n], z2 = g.h + g.zedge[n + 1];
     const double cx = a * g.dx, cy = b * g.dy, cz = 0.5 * (z1 + z2);
-    const double hx = 0.5 * g.dx, hy = 0.5 * g.dy, hz = 0.5 * g.dz;
+    const double hx = 0.5 * g.dx, hy = 0.5 * g.dy, hz = 0.5 * (z2 - z1);
     const double hd = sqrt(hx * hx + hy * hy + hz * hz);
     const double t = sqrt(cx * cx + cy * cy + cz * cz) / hd;
 

@@ -102,7 +102,9 @@ struct DevBuf {
 
 struct gf_plan {
     int nx, ny, nz;
-    double dx, dy, dz, h;
+    double dx, dy, h;
+    std::vector<double> zedge;      // nz + 1 layer-edge depths (n dz for uniform layers)
+    double *zedge_dev = nullptr;    // the same on the device, for the kernel-table kernel
     unsigned mask;
     int prec;
     int max_batch;
@@ -255,7 +257,7 @@ gf::KgenGeom kgen_geom(const gf_plan *p)
     g.py = p->py;
     g.dx = p->dx;
     g.dy = p->dy;
-    g.dz = p->dz;
+    g.zedge = p->zedge_dev;
     g.h = p->h;
     g.t_analytic = 8.0;
     g.t_gl6 = 24.0;
@@ -320,6 +322,7 @@ void free_plan(gf_plan *p)
     if (p->tw) (void)hipFree(p->tw);
     if (p->tw64 && p->tw64 != p->tw) (void)hipFree(p->tw64);
     if (p->iws) (void)hipFree(p->iws);
+    if (p->zedge_dev) (void)hipFree(p->zedge_dev);
     delete p;
 }
 
@@ -342,17 +345,13 @@ const char *gf_status_string(gf_status s)
 
 const char *gf_last_error(void) { return g_err.c_str(); }
 
-gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz, double h,
-                         unsigned components, int precision, int max_batch, void *hip_stream,
-                         gf_plan **out)
+// Shared by the uniform and the layered constructors: `edges` holds the
+// nz + 1 layer-edge depths, already checked.
+static gf_status create_plan(int nx, int ny, int nz, double dx, double dy, const double *edges, double h,
+                             unsigned components, int precision, int max_batch, void *hip_stream,
+                             gf_plan **out)
 {
-    g_err.clear();
-    if (!out) return fail(GF_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (nx < 1 || ny < 1 || nz < 1) return fail(GF_EINVAL, "grid sizes must be >= 1 (got %d,%d,%d)", nx, ny, nz);
-    if (nx > kMaxN || ny > kMaxN)
-        return fail(GF_EUNSUPPORTED, "nx, ny must be <= %d (got %d,%d)", kMaxN, nx, ny);
-    if (!(dx > 0) || !(dy > 0) || !(dz > 0) || !std::isfinite(dx) || !std::isfinite(dy) || !std::isfinite(dz))
+    if (!(dx > 0) || !(dy > 0) || !std::isfinite(dx) || !std::isfinite(dy))
         return fail(GF_EINVAL, "cell sizes must be positive and finite");
     if (!(h > 0) || !std::isfinite(h)) return fail(GF_EINVAL, "station height h must be > 0");
     if (components == 0 || (components & ~(unsigned)GF_ALL9))
@@ -370,7 +369,7 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     p->nz = nz;
     p->dx = dx;
     p->dy = dy;
-    p->dz = dz;
+    p->zedge.assign(edges, edges + nz + 1);
     p->h = h;
     p->mask = components;
     p->prec = precision;
@@ -440,6 +439,12 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     }
 
     gf_status s;
+    if ((s = hip_check(hipMalloc(&p->zedge_dev, (nz + 1) * sizeof(double)), "layer edges")) != GF_OK ||
+        (s = hip_check(hipMemcpy(p->zedge_dev, p->zedge.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice),
+                       "layer edges")) != GF_OK) {
+        free_plan(p);
+        return s;
+    }
     const int tl = 1 << p->twlog;
     {
         auto t64 = twiddle_table<double>(tl);
@@ -489,6 +494,44 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     p->plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     *out = p;
     return GF_OK;
+}
+
+static gf_status check_grid(int nx, int ny, int nz, gf_plan **out)
+{
+    g_err.clear();
+    if (!out) return fail(GF_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(GF_EINVAL, "grid sizes must be >= 1 (got %d,%d,%d)", nx, ny, nz);
+    if (nx > kMaxN || ny > kMaxN)
+        return fail(GF_EUNSUPPORTED, "nx, ny must be <= %d (got %d,%d)", kMaxN, nx, ny);
+    if ((long)nz * nx * ny > (1L << 31)) return fail(GF_EUNSUPPORTED, "model too large");
+    return GF_OK;
+}
+
+gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz, double h,
+                         unsigned components, int precision, int max_batch, void *hip_stream,
+                         gf_plan **out)
+{
+    gf_status s = check_grid(nx, ny, nz, out);
+    if (s != GF_OK) return s;
+    if (!(dz > 0) || !std::isfinite(dz)) return fail(GF_EINVAL, "cell sizes must be positive and finite");
+    std::vector<double> edges(nz + 1);
+    for (int n = 0; n <= nz; ++n) edges[n] = n * dz;
+    return create_plan(nx, ny, nz, dx, dy, edges.data(), h, components, precision, max_batch, hip_stream, out);
+}
+
+gf_status gf_plan_create_layered(int nx, int ny, int nz, double dx, double dy, const double *z_edges, double h,
+                                 unsigned components, int precision, int max_batch, void *hip_stream,
+                                 gf_plan **out)
+{
+    gf_status s = check_grid(nx, ny, nz, out);
+    if (s != GF_OK) return s;
+    if (!z_edges) return fail(GF_EINVAL, "z_edges is NULL");
+    if (!(z_edges[0] >= 0) || !std::isfinite(z_edges[0])) return fail(GF_EINVAL, "z_edges[0] must be >= 0");
+    for (int n = 0; n < nz; ++n)
+        if (!(z_edges[n + 1] > z_edges[n]) || !std::isfinite(z_edges[n + 1]))
+            return fail(GF_EINVAL, "z_edges must increase strictly (at %d)", n + 1);
+    return create_plan(nx, ny, nz, dx, dy, z_edges, h, components, precision, max_batch, hip_stream, out);
 }
 
 gf_status gf_plan_destroy(gf_plan *plan)

@@ -39,7 +39,7 @@ class Plan:
     """A geometry's resident kernel spectra (see include/gravfft.h)."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64",
-                 max_batch=0, device=None, stream=None):
+                 max_batch=0, device=None, stream=None, zedges=None):
         lib = nat.load()
         device = torch.device("cuda") if device is None else torch.device(device)
         if device.type != "cuda":
@@ -53,12 +53,24 @@ class Plan:
         self.dtype = torch.float64 if prec == nat.GF_F64 else torch.float32
         self.mask = components_mask(components)
         self.geometry = (int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(h))
+        self.zedges = None
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = _stream_handle(stream)
-            nat.check(lib.gf_plan_create(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(h),
-                                         ctypes.c_uint(self.mask), prec, int(max_batch), st, ctypes.byref(handle)),
-                      "gf_plan_create")
+            if zedges is None:
+                nat.check(lib.gf_plan_create(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(h),
+                                             ctypes.c_uint(self.mask), prec, int(max_batch), st,
+                                             ctypes.byref(handle)),
+                          "gf_plan_create")
+            else:
+                z = (ctypes.c_double * len(zedges))(*[float(v) for v in zedges])
+                if len(zedges) != int(nz) + 1:
+                    raise ValueError("zedges must hold nz + 1 depths, got %d" % len(zedges))
+                nat.check(lib.gf_plan_create_layered(int(nx), int(ny), int(nz), float(dx), float(dy), z, float(h),
+                                                     ctypes.c_uint(self.mask), prec, int(max_batch), st,
+                                                     ctypes.byref(handle)),
+                          "gf_plan_create_layered")
+                self.zedges = tuple(float(v) for v in zedges)
         self._h = handle
         info = nat.PlanInfo()
         nat.check(lib.gf_plan_get_info(self._h, ctypes.byref(info)), "gf_plan_get_info")
@@ -193,6 +205,14 @@ class Plan:
 
 def plan(nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64", max_batch=0, device=None, stream=None):
     return Plan(nx, ny, nz, dx, dy, dz, h, components, precision, max_batch, device, stream)
+
+
+def plan_layered(nx, ny, dx, dy, zedges, h, components=ALL6, precision="f64", max_batch=0, device=None,
+                 stream=None):
+    """Plan of a layered mesh: layer n spans depths [zedges[n], zedges[n+1]]
+    (len(zedges) = nz + 1, strictly increasing, zedges[0] >= 0)."""
+    nz = len(zedges) - 1
+    return Plan(nx, ny, nz, dx, dy, 0.0, h, components, precision, max_batch, device, stream, zedges=zedges)
 
 
 def forward(p, rho, d=None, workspace=None, stream=None):

@@ -84,3 +84,22 @@ def test_null_arguments(lib):
     sz = ctypes.c_size_t()
     assert lib.gf_workspace_bytes(None, 0, 1, ctypes.byref(sz)) == _native.GF_EINVAL
     assert lib.gf_plan_create(16, 16, 8, 50.0, 50.0, 50.0, 25.0, ctypes.c_uint(0x3F), 0, 0, None, None) == _native.GF_EINVAL
+
+
+@pytest.mark.parametrize("edges,what", [
+    (None, "null edges"),
+    ([0.0, 10.0, 10.0, 30.0, 40.0], "repeated edge"),
+    ([0.0, 10.0, 5.0, 30.0, 40.0], "decreasing"),
+    ([-1.0, 10.0, 20.0, 30.0, 40.0], "top above the surface"),
+    ([0.0, 10.0, float("nan"), 30.0, 40.0], "nan"),
+    ([0.0, 10.0, 20.0, 30.0, float("inf")], "inf"),
+])
+def test_layered_plan_rejects_bad_edges(lib, edges, what):
+    from paper_2005_10160_amd import _native
+    h = ctypes.c_void_p(123)
+    z = None if edges is None else (ctypes.c_double * len(edges))(*edges)
+    st = lib.gf_plan_create_layered(16, 16, 4, 50.0, 50.0, z, 25.0, ctypes.c_uint(0x3F), 0, 0, None,
+                                    ctypes.byref(h))
+    assert st == _native.GF_EINVAL, what
+    assert h.value is None
+    assert lib.gf_last_error().decode() != ""
