@@ -99,11 +99,6 @@ void orc_set_threads(int n)
 /* Corner terms of the closed forms (without G rho and without mu).          */
 /* ------------------------------------------------------------------------ */
 
-/* a * v where v grows at most like ln(1/|a|) or stays bounded as a -> 0:
- * the product's limit at a = 0 is 0 (corners on the axes of a box that the
- * station touches). */
-static ld times(ld a, ld v) { return a == 0 ? 0 : a * v; }
-
 static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
 {
     ld x2 = x * x, y2 = y * y, z2 = z * z;
@@ -112,8 +107,14 @@ static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
     ld syz = sqrtl(y2 + z2);
     ld ash_y = asinhl(y / sxz);        /* = ln(y + r) - ln sqrt(x^2+z^2) */
     ld ash_x = asinhl(x / syz);        /* = ln(x + r) - ln sqrt(y^2+z^2) */
+    /* On a corner at x = y = 0 (a station over a cell edge) the terms
+     * y asinh(z/sqrt(x^2+y^2)) and x atan(y z / (x r)) have the limit 0:
+     * the factor vanishes while asinh grows like ln(1/|y|) and atan stays
+     * bounded. */
     ld sxy = sqrtl(x2 + y2);
     ld ash_z = sxy > 0 ? asinhl(z / sxy) : 0;   /* only ever multiplied by x or y */
+    ld at_x = x != 0 ? atanl((y * z) / (x * r)) : 0;
+    ld at_y = y != 0 ? atanl((x * z) / (y * r)) : 0;
     ld at_z = atanl((x * y) / (z * r));
     f[C_GZ] = -(x * ash_y + y * ash_x - z * at_z);
     f[C_GXX] = -atan2l(y * z, x * r);
@@ -122,8 +123,8 @@ static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
     f[C_GXY] = logl(z + r);
     f[C_GXZ] = ash_y;
     f[C_GYZ] = ash_x;
-    f[C_GX] = -(z * ash_y + times(y, ash_z) - times(x, x != 0 ? atanl((y * z) / (x * r)) : 0));
-    f[C_GY] = -(times(x, ash_z) + z * ash_x - times(y, y != 0 ? atanl((x * z) / (y * r)) : 0));
+    f[C_GX] = -(z * ash_y + y * ash_z - x * at_x);
+    f[C_GY] = -(x * ash_z + z * ash_x - y * at_y);
 }
 
 /* mu for corner (i,j,k), each 0 = lower bound, 1 = upper bound. */

@@ -412,3 +412,19 @@ def test_layered_mesh_buried_top_and_blocks(orc):
                 [0.0, 10.0, np.nan, 30.0, 40.0]):
         with pytest.raises(ValueError):
             orc.forward_grid(g, rho[:4, :6, :8], zedges=bad)
+
+
+def test_layered_offset_table_is_a_shifted_uniform_layer(orc):
+    """The offset table of layer n of a stretched mesh equals layer 0 of a
+    uniform mesh whose top is z_n deeper and whose layers are z_{n+1} - z_n
+    thick: the same prisms (eq. 7 per layer), in both table modes."""
+    g = Geometry(9, 6, 5, 20.0, 30.0, 1.0, 7.0)
+    z = np.concatenate([[3.0], 3.0 + np.cumsum(4.0 * 1.6 ** np.arange(g.nz))])
+    for n in range(g.nz):
+        u = Geometry(g.nx, g.ny, 1, g.dx, g.dy, z[n + 1] - z[n], g.h + z[n])
+        for mode in (0, 1):
+            got = orc.kernel_table(g, n, mode=mode, zedges=z)
+            want = orc.kernel_table(u, 0, mode=mode)
+            for c in range(orc.NCOMP):
+                s = np.abs(want[c]).max()
+                assert np.abs(got[c] - want[c]).max() <= 1e-14 * s, (n, mode, c)
