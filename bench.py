@@ -13,7 +13,8 @@ the number of kernel-matrix entries the operator applies per second
 
 One JSON line is printed.  Besides the headline FP64 forward it carries the
 FP32 path, the adjoint, a live roofline of the dominant kernel (the column
-pass), the same model with other component sets (gz with the first
+pass) with the device's practical copy and read rates beside the 8 TB/s
+peak, the same model with other component sets (gz with the first
 derivatives gx, gy; all nine outputs) and on a depth-stretched layered mesh,
 the batched inversion-step workload (512^2 x 128, 32 models, forward
 and adjoint in both precisions), the CPU oracle timed on a bounded sample,
@@ -193,6 +194,44 @@ def batched_step(steps, warmup):
     return out
 
 
+def stream_bandwidth(dev, gib=2, reps=10):
+    """Practical streaming rates of the device, timed with HIP events: a
+    plain device-to-device copy of `gib` GiB (GB/s of bytes read plus
+    written) and a sum over 2*`gib` GiB (read-only, like the column pass)."""
+    import torch
+    n = (gib << 30) // 8
+    src = torch.ones(2 * n, dtype=torch.float64, device=dev)
+    dst = torch.empty(n, dtype=torch.float64, device=dev)
+    out = torch.empty((), dtype=torch.float64, device=dev)
+
+    def rate(fn, nbytes):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return nbytes / (a.elapsed_time(b) / reps * 1e-3) / 1e9
+
+    copy = rate(lambda: dst.copy_(src[:n]), 2.0 * n * 8)
+    read = rate(lambda: torch.sum(src, dim=0, out=out), 2.0 * n * 8)
+    del src, dst, out
+    return copy, read
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(g, rho_np, n_stations, threads):
     import oracle
     if threads:
@@ -203,6 +242,7 @@ def cpu_baseline(g, rho_np, n_stations, threads):
     oracle.forward(g, rho_np, st)
     dt = time.perf_counter() - t0
     evals = len(st) * g.nm * 6
+    full = 6.0 * g.nd * g.nm
     return {
         "value": evals / dt,
         "unit": "kernel-evals/s",
@@ -210,6 +250,8 @@ def cpu_baseline(g, rho_np, n_stations, threads):
         "kind": "oracle",
         "sample": "long-double direct sum (eq. 3) of the same 1024^2x100 model at %d station(s), "
                   "all %d cells, 6 components counted; %.1f s wall" % (len(st), g.nm, dt),
+        "cpu": cpu_model(),
+        "extrapolated_full_apply_s": full / (evals / dt),
     }
 
 
@@ -315,6 +357,15 @@ def main():
                 "kernel": "col_forward_ws_kernel (FFT along y + layer reduction + inverse FFT)",
                 "algorithmic_bytes_per_launch": alg_bytes, "layer_splits": S,
                 "kernel_ms": round(col_ms, 4)}
+    # whole-apply compulsory bytes: resident spectra once, density in, data out
+    s_el = 8 if args.precision == "f64" else 4
+    compulsory = (p.spectra_bytes + s_el * (g.nz * g.nx * g.ny + 6 * g.nx * g.ny))
+    pct = np.percentile(per, [10, 50, 90])
+    log("bench: device streaming rates")
+    copy_gbs, read_gbs = stream_bandwidth(dev)
+    roofline["practical_copy_GBs"] = round(copy_gbs, 1)
+    roofline["practical_read_GBs"] = round(read_gbs, 1)
+    roofline["frac_of_read"] = round(achieved / read_gbs, 4)
     line = {
         "metric": METRIC,
         "value": value,
@@ -334,6 +385,11 @@ def main():
                    "precision": args.precision},
         "roofline": roofline,
         "median_ms": statistics.median(per),
+        "p10_ms": float(pct[0]),
+        "p90_ms": float(pct[2]),
+        "apply_compulsory": {"bytes": int(compulsory),
+                             "GBs": round(compulsory / (ms_per_step * 1e-3) / 1e9, 1),
+                             "frac_of_8TBs": round(compulsory / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
         "plan_ms": round(main_res["plan_ms"], 1),
         "spectra_bytes": main_res["spectra_bytes"],
         "pass_ms": [round(float(x), 4) for x in main_res["passes"].mean(axis=0)],
