@@ -35,10 +35,7 @@ import itertools
 import threading
 import time
 from dataclasses import dataclass, field
-from typing import Any, Optional
-
-COMPONENT_COUNT = 7
-
+from typing import Any, Optional, Tuple
 
 @dataclass(frozen=True)
 class GeometryKey:
@@ -50,10 +47,18 @@ class GeometryKey:
     dz: float
     h: float
     components: int
+    zedges: Optional[Tuple[float, ...]] = None   # layered mesh: nz + 1 layer-edge depths (dz unused)
 
     @property
     def n_out(self):
         return bin(self.components & 0x1FF).count("1")
+
+    @property
+    def n_spec(self):
+        spec = self.components & 0x1BF        # every component but gzz has a spectrum
+        if self.components & 0x40:
+            spec |= 0x12                       # gzz = -(gxx + gyy)
+        return bin(spec).count("1")
 
 
 @dataclass
@@ -91,11 +96,7 @@ def _circulant(n):
 def spectra_bytes(key: GeometryKey, elem: int) -> int:
     """Resident spectra of a plan: one real per frequency of the quarter plane
     for each stored component and layer."""
-    spec = key.components & 0x1BF        # every component but gzz has a spectrum
-    if key.components & 0x40:
-        spec |= 0x12                       # gzz = -(gxx + gyy)
-    n_spec = bin(spec).count("1")
-    return n_spec * key.nz * (_circulant(key.nx) // 2 + 1) * (_circulant(key.ny) // 2 + 1) * elem
+    return key.n_spec * key.nz * (_circulant(key.nx) // 2 + 1) * (_circulant(key.ny) // 2 + 1) * elem
 
 
 def io_bytes(key: GeometryKey, op: str, batch: int, elem: int) -> int:
@@ -292,8 +293,12 @@ class GpuExecutor:
     def plan_for(self, key):
         p = self.plans.get(key)
         if p is None:
-            p = self.op_mod.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components,
-                                 self.precision, device=self.device, stream=self.plan_stream)
+            if key.zedges is None:
+                p = self.op_mod.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components,
+                                     self.precision, device=self.device, stream=self.plan_stream)
+            else:
+                p = self.op_mod.plan_layered(key.nx, key.ny, key.dx, key.dy, key.zedges, key.h, key.components,
+                                             self.precision, device=self.device, stream=self.plan_stream)
             self.plans[key] = p
         return p
 
@@ -303,11 +308,17 @@ class GpuExecutor:
         p = self.plans.get(key)
         if p is not None:
             return p.workspace_bytes(op, batch)
+        # forward: row-transformed model, up to 32 layer splits of partial
+        # data and up to 32 Nyquist chunks; adjoint: the residual's spectra
+        # and one model-sized slab per group of six spectra
         ux = _circulant(key.nx) // 2 + 1
-        nspec = 6
-        splits = 8
-        per = 2 * self.elem * ux * key.ny
-        return per * batch * (key.nz + splits * nspec)
+        nspec = key.n_spec
+        groups = (nspec + 5) // 6
+        splits = 32
+        per = 2 * self.elem * ux * (key.ny + 1)
+        fwd = per * batch * (key.nz + splits * nspec) + self.elem * splits * batch * nspec * (key.ny + 1)
+        adj = per * batch * (nspec + groups * key.nz)
+        return max(fwd, adj)
 
     def is_resident(self, key):
         return key in self.plans

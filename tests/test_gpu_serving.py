@@ -33,13 +33,19 @@ def test_served_equals_alone(gf, orc):
     from paper_2005_10160_amd.serve import GeometryKey, GpuExecutor, Request, Server
     rng = np.random.default_rng(8)
     specs = []
-    for i in range(14):
+    for i in range(16):
         n = int(rng.choice([64, 128]))
         nz = int(rng.choice([8, 16]))
-        comps = 0x3F if rng.random() < 0.5 else 0x1
+        # gz, the six stored components, all nine (two column-pass groups),
+        # gz with the first derivatives
+        comps = int(rng.choice([0x3F, 0x1, 0x1FF, 0x181]))
         op = "forward" if rng.random() < 0.5 else "adjoint"
         B = int(rng.integers(1, 5))
-        key = GeometryKey(n, n, nz, 20.0, 20.0, 20.0, 10.0, comps)
+        # some geometries are layered meshes (thickening layers, buried top)
+        zedges = None
+        if rng.random() < 0.3:
+            zedges = tuple(float(v) for v in 5.0 + np.concatenate([[0.0], np.cumsum(6.0 * 1.2 ** np.arange(nz))]))
+        key = GeometryKey(n, n, nz, 20.0, 20.0, 20.0, 10.0, comps, zedges)
         C = key.n_out
         shape = (B, nz, n, n) if op == "forward" else (B, C, n, n)
         x = torch.from_numpy(rng.uniform(-500, 500, size=shape).astype(np.float32)).pin_memory()
@@ -61,7 +67,11 @@ def test_served_equals_alone(gf, orc):
     plans = {}
     for (key, op, x), r in zip(specs, reqs):
         if key not in plans:
-            plans[key] = gf.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components, "f32")
+            if key.zedges is None:
+                plans[key] = gf.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components, "f32")
+            else:
+                plans[key] = gf.plan_layered(key.nx, key.ny, key.dx, key.dy, key.zedges, key.h, key.components,
+                                             "f32")
         p = plans[key]
         xd = x.cuda()
         alone = (p.forward(xd) if op == "forward" else p.adjoint(xd)).cpu()
@@ -72,17 +82,43 @@ def test_served_equals_alone(gf, orc):
     for p in plans.values():
         p.close()
 
-    # one served forward against the oracle
+    # served forwards against the oracle: the first uniform and the first
+    # layered one
     from synth import Geometry
+    seen = set()
     for (key, op, x), r in zip(specs, reqs):
-        if op == "forward":
+        kind = key.zedges is not None
+        if op == "forward" and kind not in seen:
+            seen.add(kind)
             g = Geometry(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h)
             st = np.array([(0, 0), (key.nx // 2, key.ny // 3), (key.nx - 1, key.ny - 1)])
-            want = orc.forward(g, x[0].double().numpy(), st)
+            want = orc.forward(g, x[0].double().numpy(), st, zedges=key.zedges)
             got = r.result[0].double().numpy()
-            comps = [c for c in range(7) if key.components >> c & 1]
+            comps = [c for c in range(9) if key.components >> c & 1]
             for i, c in enumerate(comps):
                 gv = got[i][st[:, 1], st[:, 0]]
                 e = np.linalg.norm(gv - want[:, c]) / np.linalg.norm(want[:, c])
-                assert e <= 1e-5, (c, e)
-            break
+                assert e <= 1e-5, (key, c, e)
+    assert seen, "no served forward to check"
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_workspace_estimate_bounds_the_plan(gf, prec):
+    """Admission sizes a request's workspace before its plan exists; that
+    estimate must not fall below what the plan then asks for."""
+    from paper_2005_10160_amd.serve import GeometryKey, GpuExecutor
+    ex = GpuExecutor(prec, 1)
+    cases = [(64, 8, 0x1), (64, 8, 0x1FF), (100, 37, 0x1FF), (128, 16, 0x3F), (33, 5, 0x181), (96, 3, 0x7F)]
+    for n, nz, comps in cases:
+        for zedges in (None, tuple(float(v) for v in np.cumsum(np.r_[0.0, 3.0 * 1.3 ** np.arange(nz)]))):
+            key = GeometryKey(n, n + 7, nz, 20.0, 20.0, 20.0, 10.0, comps, zedges)
+            est = {(op, B): ex.workspace_bytes(key, op, B) for op in ("forward", "adjoint") for B in (1, 3, 16)}
+            if zedges is None:
+                p = gf.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, comps, prec)
+            else:
+                p = gf.plan_layered(key.nx, key.ny, key.dx, key.dy, zedges, key.h, comps, prec)
+            for (op, B), e in est.items():
+                need = p.workspace_bytes(op, B)
+                assert need <= e, (key, op, B, need, e)
+            p.close()
+    ex.close()
