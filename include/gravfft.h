@@ -26,6 +26,8 @@
  *     rho  [B][nz][ny][nx]          density models
  *     d    [B][C][ny][nx]           data; C = popcount(components), the
  *                                   components in ascending bit order
+ *                                   ([B][nt][C][ny][nx] for a plan of nt
+ *                                   observation levels, gf_plan_create_levels)
  *     r    [B][C][ny][nx]           adjoint input (same layout as d)
  *     g    [B][nz][ny][nx]          adjoint output (same layout as rho)
  * Element type: double for GF_F64, float for GF_F32.
@@ -100,6 +102,7 @@ typedef struct {
     size_t spectra_bytes;  /* resident spectra                                  */
     size_t internal_workspace_bytes;
     double plan_ms;        /* wall time of gf_plan_create (kernel table + FFTs) */
+    int n_levels;          /* observation levels (1 unless gf_plan_create_levels) */
 } gf_plan_info_t;
 
 /*
@@ -146,6 +149,25 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
 gf_status gf_plan_create_layered(int nx, int ny, int nz, double dx, double dy, const double *z_edges, double h,
                                  unsigned components, int precision, int max_batch, void *hip_stream,
                                  gf_plan **out);
+
+/*
+ * The equal-dimension survey of section 2.2 (Fig. 2a): the data are
+ * three-dimensional as the model is, stations on n_levels horizontal planes
+ * spaced dz apart, level t (t = 0 .. n_levels-1) at height h + t dz above
+ * the model top, one station above each cell centre per level.  By
+ * translation equivalence in depth (eq. 10) the block of level t and layer n
+ * is the single-plane block of layer n + t, so the plan holds the spectra of
+ * nz + n_levels - 1 layer offsets (eq. 11's 2nz when n_levels = nz) and
+ * level t sums the window of them starting at offset t.
+ *   n_levels  >= 1 (1 gives the plan of gf_plan_create)
+ *   d, r      [B][n_levels][C][ny][nx]; rho and g as for a single plane
+ * Other arguments as gf_plan_create.  gf_debug_kernel_table and
+ * gf_debug_spectrum index the nz + n_levels - 1 layer offsets; the pass
+ * timing's column figure also covers all inverse row passes but the last.
+ */
+gf_status gf_plan_create_levels(int nx, int ny, int nz, double dx, double dy, double dz, double h, int n_levels,
+                                unsigned components, int precision, int max_batch, void *hip_stream,
+                                gf_plan **out);
 
 /* Free a plan and its device memory.  NULL is accepted.  The caller must have
  * finished every call that uses the plan. */

@@ -281,3 +281,34 @@ def blocks_at_stations(geom, blocks, stations, zedges=None):
     if rc != 0:
         raise ValueError("bad blocks")
     return out
+
+
+class _AtHeight:
+    """The geometry `geom` with its station plane at height `h`."""
+
+    def __init__(self, geom, h):
+        self.nx, self.ny, self.nz = geom.nx, geom.ny, geom.nz
+        self.dx, self.dy, self.dz = geom.dx, geom.dy, geom.dz
+        self.h = h
+
+
+def forward_levels(geom, rho, levels, stations=None):
+    """Equal-dimension survey (section 2.2, Fig. 2a): stations on `levels`
+    planes at heights h + t dz, t = 0 .. levels-1, above the model top; each
+    level is the direct sum (eq. 3) of its own plane.  Returns
+    (nb, levels, nst, NCOMP) (nb dropped for 3-D rho)."""
+    out = [forward(_AtHeight(geom, geom.h + t * geom.dz), rho, stations) for t in range(levels)]
+    return np.stack(out, axis=-3)
+
+
+def adjoint_levels(geom, r, mask, levels, cells=None):
+    """Adjoint of forward_levels: sum over levels of each plane's adjoint.
+    r: (levels, NCOMP, ny, nx) or (nb, levels, NCOMP, ny, nx)."""
+    r = np.asarray(r, dtype=np.float64)
+    lev_axis = r.ndim - 4
+    total = None
+    for t in range(levels):
+        rt = np.ascontiguousarray(np.take(r, t, axis=lev_axis))
+        a = adjoint(_AtHeight(geom, geom.h + t * geom.dz), rt, mask, cells)
+        total = a if total is None else total + a
+    return total

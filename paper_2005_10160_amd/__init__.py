@@ -30,10 +30,11 @@ from .operator import (
     forward,
     plan,
     plan_layered,
+    plan_levels,
 )
 
 __all__ = [
     "ALL6", "ALL7", "ALL9", "COMPONENTS", "GZ", "GXX", "GXY", "GXZ", "GYY", "GYZ", "GZZ", "GX", "GY",
     "GravityForward", "GravityOperator", "Plan", "adjoint", "components_mask",
-    "forward", "plan", "plan_layered",
+    "forward", "plan", "plan_layered", "plan_levels",
 ]

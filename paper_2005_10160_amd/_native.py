@@ -17,7 +17,7 @@ GF_F64, GF_F32 = 0, 1
 GF_OP_FORWARD, GF_OP_ADJOINT = 0, 1
 
 EXPORTED = (
-    "gf_plan_create", "gf_plan_create_layered", "gf_plan_destroy", "gf_plan_get_info", "gf_plan_bytes",
+    "gf_plan_create", "gf_plan_create_layered", "gf_plan_create_levels", "gf_plan_destroy", "gf_plan_get_info", "gf_plan_bytes",
     "gf_workspace_bytes", "gf_forward", "gf_adjoint", "gf_status_string",
     "gf_last_error", "gf_debug_kernel_table", "gf_debug_spectrum",
     "gf_plan_set_timing", "gf_plan_last_pass_ms",
@@ -33,6 +33,7 @@ class PlanInfo(ctypes.Structure):
         ("precision", ctypes.c_int), ("max_batch", ctypes.c_int),
         ("spectra_bytes", ctypes.c_size_t), ("internal_workspace_bytes", ctypes.c_size_t),
         ("plan_ms", ctypes.c_double),
+        ("n_levels", ctypes.c_int),
     ]
 
 
@@ -62,6 +63,8 @@ def load(path=None):
         lib.gf_plan_create.restype = i
         lib.gf_plan_create_layered.argtypes = [i, i, i, d, d, pd, d, u, i, i, vp, ctypes.POINTER(vp)]
         lib.gf_plan_create_layered.restype = i
+        lib.gf_plan_create_levels.argtypes = [i, i, i, d, d, d, d, i, u, i, i, vp, ctypes.POINTER(vp)]
+        lib.gf_plan_create_levels.restype = i
         lib.gf_plan_destroy.argtypes = [vp]
         lib.gf_plan_destroy.restype = i
         lib.gf_plan_get_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]

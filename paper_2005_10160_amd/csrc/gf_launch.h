@@ -56,12 +56,14 @@ int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int
 
 // Inverse row transform: X(b,o,y)[u] = sum_split sum_i w[o][i] D[split][b][src[o][i]][u][y],
 // then real rows of length px, of which the first nx_out are written, times
-// `scale`, to out[b][o][y][x].  With nq.Sny > 0 the imaginary field of
-// packed unit 0 (the Nyquist bin) is instead sum_chunk sum_i w[o][i]
-// Dny[chunk][b][src[o][i]][y].
+// `scale`, to out + b*out_bstride + (o*rows + y)*nx_out (out_bstride 0: the
+// items are packed, nsub*rows*nx_out apart), or added to what is there when
+// `accumulate`.  With nq.Sny > 0 the imaginary field of packed unit 0 (the
+// Nyquist bin) is instead sum_chunk sum_i w[o][i] Dny[chunk][b][src[o][i]][y].
 int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nsplit, int nsrc,
                    int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, const NyqSplit &nq,
-                   void *out, int nx_out, double scale, const void *tw, int twlog, hipStream_t st);
+                   void *out, int nx_out, double scale, const void *tw, int twlog, hipStream_t st,
+                   long out_bstride = 0, bool accumulate = false);
 
 // Column data are stored per slab as [unit][y] with M = px/2 units and a
 // leading dimension ldc >= ny (even, so that columns are 16-byte aligned): unit u

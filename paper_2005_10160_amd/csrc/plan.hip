@@ -102,8 +102,13 @@ struct DevBuf {
 
 struct gf_plan {
     int nx, ny, nz;
+    // Observation levels: nt planes of stations at heights h + t dz,
+    // t = 0..nt-1 (nt = 1: the single plane of section 2.1).  Level t sees
+    // model layer n where the single-plane geometry has layer n + t, so the
+    // spectra cover nzs = nz + nt - 1 layer offsets (eq. 10-11).
+    int nt = 1, nzs = 0;
     double dx, dy, h;
-    std::vector<double> zedge;      // nz + 1 layer-edge depths (n dz for uniform layers)
+    std::vector<double> zedge;      // nzs + 1 layer-edge depths (n dz for uniform layers)
     double *zedge_dev = nullptr;    // the same on the device, for the kernel-table kernel
     unsigned mask;
     int prec;
@@ -118,7 +123,7 @@ struct gf_plan {
     unsigned imag_mask, yodd_mask;  // over spectral slots
     // Spectral slots in groups of at most kColMaxSpec, one column-pass
     // launch each; group g holds slots [grp_c0[g], grp_c0[g] + grp_cs[g]) and
-    // its spectra are stored apart as [nz][M+1][grp_cs[g]][QP].
+    // its spectra are stored apart as [nzs][M+1][grp_cs[g]][QP].
     int ngrp;
     int grp_c0[2], grp_cs[2];
     gf::RowCombo out_combo;         // output o from spectral slots
@@ -136,7 +141,15 @@ struct gf_plan {
     bool ev_recorded[2] = {false, false};
 
     bool fp64() const { return prec == GF_F64; }
-    char *spec_group(int g) const { return (char *)spec + elem() * (size_t)nz * U * QP * grp_c0[g]; }
+    char *spec_group(int g) const { return (char *)spec + elem() * (size_t)nzs * U * QP * grp_c0[g]; }
+    // spectra of group g from spectral layer t on (the window of level t)
+    char *spec_window(int g, int t) const
+    {
+        return spec_group(g) + elem() * (size_t)t * U * grp_cs[g] * QP;
+    }
+    // levels per chunk of the adjoint (each level of a chunk has its own
+    // residual spectra and layer columns; the inverse rows sum the chunk)
+    int adj_chunk() const { return std::min(nt, 4); }
     unsigned grp_bits(unsigned m, int g) const { return (m >> grp_c0[g]) & ((1u << grp_cs[g]) - 1u); }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
     size_t celem() const { return 2 * elem(); }
@@ -221,7 +234,7 @@ struct gf_plan {
             fwd_split(B, &S, &l);
             return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * n_spec) + nyq_bytes(B);
         }
-        return celem() * (size_t)M * ldc * ((size_t)B * n_spec + (size_t)ngrp * B * nz);
+        return celem() * (size_t)M * ldc * (size_t)adj_chunk() * ((size_t)B * n_spec + (size_t)ngrp * B * nz);
     }
 };
 
@@ -272,7 +285,7 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
     const size_t budget = (size_t)2 << 30;
     int nl = (int)(budget / (per_pair * p->grp_cs[0]));
     if (nl < 1) nl = 1;
-    if (nl > p->nz) nl = p->nz;
+    if (nl > p->nzs) nl = p->nzs;
     DevBuf E, Rk;
     gf_status s;
     if ((s = hip_check(hipMalloc(&E.p, field * sizeof(double) * nl * p->grp_cs[0]), "kernel field")) != GF_OK)
@@ -286,8 +299,8 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
     ident.identity = 1;
     for (int gr = 0; gr < p->ngrp; ++gr) {
         const int cs = p->grp_cs[gr];
-        for (int n0 = 0; n0 < p->nz; n0 += nl) {
-            const int nlc = std::min(nl, p->nz - n0);
+        for (int n0 = 0; n0 < p->nzs; n0 += nl) {
+            const int nlc = std::min(nl, p->nzs - n0);
             const int npair = nlc * cs;
             if ((s = hip_check(hipMemsetAsync(E.p, 0, field * sizeof(double) * npair, st), "memset")) != GF_OK)
                 return s;
@@ -296,7 +309,7 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
             if (gf::launch_row_r2c(true, p->px, E.p, p->px, p->px, p->py, p->py, npair, npair, 1, ident, Rk.p,
                                    p->tw64, p->twlog, st) != 0)
                 return fail(GF_EDEVICE, "kernel row transform launch failed");
-            if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec_group(gr), nlc, n0, cs, p->nz, p->M,
+            if (gf::launch_col_kgen(p->fp64(), p->py, Rk.p, p->spec_group(gr), nlc, n0, cs, p->nzs, p->M,
                                     p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr), p->tw64,
                                     p->twlog, st) != 0)
                 return fail(GF_EDEVICE, "kernel column transform launch failed");
@@ -345,9 +358,10 @@ const char *gf_status_string(gf_status s)
 
 const char *gf_last_error(void) { return g_err.c_str(); }
 
-// Shared by the uniform and the layered constructors: `edges` holds the
-// nz + 1 layer-edge depths, already checked.
-static gf_status create_plan(int nx, int ny, int nz, double dx, double dy, const double *edges, double h,
+// Shared by the constructors: nt observation levels; `edges` holds the
+// nz + nt layer-edge depths of the nz + nt - 1 spectral layers, already
+// checked.
+static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double dy, const double *edges, double h,
                              unsigned components, int precision, int max_batch, void *hip_stream,
                              gf_plan **out)
 {
@@ -367,9 +381,11 @@ static gf_status create_plan(int nx, int ny, int nz, double dx, double dy, const
     p->nx = nx;
     p->ny = ny;
     p->nz = nz;
+    p->nt = nt;
+    p->nzs = nz + nt - 1;
     p->dx = dx;
     p->dy = dy;
-    p->zedge.assign(edges, edges + nz + 1);
+    p->zedge.assign(edges, edges + p->nzs + 1);
     p->h = h;
     p->mask = components;
     p->prec = precision;
@@ -439,8 +455,8 @@ static gf_status create_plan(int nx, int ny, int nz, double dx, double dy, const
     }
 
     gf_status s;
-    if ((s = hip_check(hipMalloc(&p->zedge_dev, (nz + 1) * sizeof(double)), "layer edges")) != GF_OK ||
-        (s = hip_check(hipMemcpy(p->zedge_dev, p->zedge.data(), (nz + 1) * sizeof(double), hipMemcpyHostToDevice),
+    if ((s = hip_check(hipMalloc(&p->zedge_dev, (p->nzs + 1) * sizeof(double)), "layer edges")) != GF_OK ||
+        (s = hip_check(hipMemcpy(p->zedge_dev, p->zedge.data(), (p->nzs + 1) * sizeof(double), hipMemcpyHostToDevice),
                        "layer edges")) != GF_OK) {
         free_plan(p);
         return s;
@@ -475,7 +491,7 @@ static gf_status create_plan(int nx, int ny, int nz, double dx, double dy, const
             return fail(GF_EUNSUPPORTED, "transform length %d with %d components does not fit in LDS", p->py,
                         p->grp_cs[g]);
         }
-    p->spec_bytes = (size_t)nz * p->U * p->n_spec * p->QP * p->elem();
+    p->spec_bytes = (size_t)p->nzs * p->U * p->n_spec * p->QP * p->elem();
     if ((s = hip_check(hipMalloc(&p->spec, p->spec_bytes), "spectra")) != GF_OK) {
         free_plan(p);
         return s;
@@ -517,7 +533,23 @@ gf_status gf_plan_create(int nx, int ny, int nz, double dx, double dy, double dz
     if (!(dz > 0) || !std::isfinite(dz)) return fail(GF_EINVAL, "cell sizes must be positive and finite");
     std::vector<double> edges(nz + 1);
     for (int n = 0; n <= nz; ++n) edges[n] = n * dz;
-    return create_plan(nx, ny, nz, dx, dy, edges.data(), h, components, precision, max_batch, hip_stream, out);
+    return create_plan(nx, ny, nz, 1, dx, dy, edges.data(), h, components, precision, max_batch, hip_stream, out);
+}
+
+gf_status gf_plan_create_levels(int nx, int ny, int nz, double dx, double dy, double dz, double h, int n_levels,
+                                unsigned components, int precision, int max_batch, void *hip_stream,
+                                gf_plan **out)
+{
+    gf_status s = check_grid(nx, ny, nz, out);
+    if (s != GF_OK) return s;
+    if (!(dz > 0) || !std::isfinite(dz)) return fail(GF_EINVAL, "cell sizes must be positive and finite");
+    if (n_levels < 1) return fail(GF_EINVAL, "n_levels must be >= 1 (got %d)", n_levels);
+    if ((long)(nz + n_levels - 1) * nx * ny > (1L << 31)) return fail(GF_EUNSUPPORTED, "model too large");
+    const int nzs = nz + n_levels - 1;
+    std::vector<double> edges(nzs + 1);
+    for (int n = 0; n <= nzs; ++n) edges[n] = n * dz;
+    return create_plan(nx, ny, nz, n_levels, dx, dy, edges.data(), h, components, precision, max_batch, hip_stream,
+                       out);
 }
 
 gf_status gf_plan_create_layered(int nx, int ny, int nz, double dx, double dy, const double *z_edges, double h,
@@ -531,7 +563,7 @@ gf_status gf_plan_create_layered(int nx, int ny, int nz, double dx, double dy, c
     for (int n = 0; n < nz; ++n)
         if (!(z_edges[n + 1] > z_edges[n]) || !std::isfinite(z_edges[n + 1]))
             return fail(GF_EINVAL, "z_edges must increase strictly (at %d)", n + 1);
-    return create_plan(nx, ny, nz, dx, dy, z_edges, h, components, precision, max_batch, hip_stream, out);
+    return create_plan(nx, ny, nz, 1, dx, dy, z_edges, h, components, precision, max_batch, hip_stream, out);
 }
 
 gf_status gf_plan_destroy(gf_plan *plan)
@@ -546,6 +578,7 @@ gf_status gf_plan_get_info(const gf_plan *p, gf_plan_info_t *info)
     info->nx = p->nx;
     info->ny = p->ny;
     info->nz = p->nz;
+    info->n_levels = p->nt;
     info->px = p->px;
     info->py = p->py;
     info->n_out = p->n_out;
@@ -608,21 +641,29 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
                            p->tw, p->twlog, st) != 0)
         return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
     mark(p, GF_OP_FORWARD, 1, st);
-    for (int gr = 0; gr < p->ngrp; ++gr) {
-        const int c0 = p->grp_c0[gr];
-        gf::NyqSplit nqg = nq;
-        if (nqg.Dny) nqg.Dny = (char *)nqg.Dny + p->elem() * (size_t)c0 * p->ldc;
-        if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec_group(gr), D + p->celem() * (size_t)c0 * p->M * p->ldc,
-                                   batch, p->nz, p->M, p->ny, p->ldc, p->grp_cs[gr], p->n_spec, S, lps, nqg,
-                                   p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr), p->tw, p->twlog,
-                                   st) != 0)
-            return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
-    }
-    mark(p, GF_OP_FORWARD, 2, st);
+    // level t: the layer sum over the spectra window starting at spectral
+    // layer t, into d[b][t]
+    const size_t plane = (size_t)p->nx * p->ny;
+    const long dstride = (long)p->nt * p->n_out * (long)plane;
     const double scale = kGrav / ((double)p->py * p->M);
-    if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->M * p->ldc, S, p->n_spec, p->ny,
-                           p->ldc, p->n_out, batch, p->out_combo, nq, d, p->nx, scale, p->tw, p->twlog, st) != 0)
-        return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    for (int t = 0; t < p->nt; ++t) {
+        for (int gr = 0; gr < p->ngrp; ++gr) {
+            const int c0 = p->grp_c0[gr];
+            gf::NyqSplit nqg = nq;
+            if (nqg.Dny) nqg.Dny = (char *)nqg.Dny + p->elem() * (size_t)c0 * p->ldc;
+            if (gf::launch_col_forward(p->fp64(), p->py, R, p->spec_window(gr, t),
+                                       D + p->celem() * (size_t)c0 * p->M * p->ldc, batch, p->nz, p->M, p->ny, p->ldc,
+                                       p->grp_cs[gr], p->n_spec, S, lps, nqg, p->grp_bits(p->imag_mask, gr),
+                                       p->grp_bits(p->yodd_mask, gr), p->tw, p->twlog, st) != 0)
+                return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+        }
+        if (t == p->nt - 1) mark(p, GF_OP_FORWARD, 2, st);
+        if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * p->n_spec * p->M * p->ldc, S, p->n_spec, p->ny,
+                               p->ldc, p->n_out, batch, p->out_combo, nq,
+                               (char *)d + p->elem() * (size_t)t * p->n_out * plane, p->nx, scale, p->tw, p->twlog,
+                               st, dstride, false) != 0)
+            return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    }
     mark(p, GF_OP_FORWARD, 3, st);
     return GF_OK;
 }
@@ -639,32 +680,46 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
     p->adj_split(batch, &S, &lps);
     gf::NyqSplit nq{nullptr, 0, 0};
     p->nyq_split(&nq.Sny, &nq.lps_ny);
-    char *R = (char *)workspace;
-    char *Gt = R + p->celem() * (size_t)batch * p->n_spec * p->M * p->ldc;
-    mark(p, GF_OP_ADJOINT, 0, st);
-    if (gf::launch_row_r2c(p->fp64(), p->px, r, p->nx, p->nx, p->ny, p->ldc, p->n_spec, p->n_out, batch,
-                           p->in_combo, R, p->tw, p->twlog, st) != 0)
-        return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
-    mark(p, GF_OP_ADJOINT, 1, st);
-    // each group writes its own layer columns; the inverse row pass sums the
-    // groups as it sums split partials
+    // levels in chunks of Tc: per level its residual's row transform and
+    // column passes into its own layer-column slabs (one per component
+    // group); the inverse row pass sums a chunk's slabs and adds the chunk
+    // to g after the first
+    const int Tc = p->adj_chunk();
+    const size_t rstride = (size_t)batch * p->n_spec * p->M * p->ldc;
     const size_t gstride = (size_t)batch * p->nz * p->M * p->ldc;
-    for (int gr = 0; gr < p->ngrp; ++gr) {
-        const int c0 = p->grp_c0[gr];
-        if (gf::launch_col_adjoint(p->fp64(), p->py, R + p->celem() * (size_t)c0 * p->M * p->ldc, p->spec_group(gr),
-                                   Gt + p->celem() * gr * gstride, batch, p->nz, p->M, p->ny, p->ldc, p->grp_cs[gr],
-                                   p->n_spec, S, lps, nq, p->grp_bits(p->imag_mask, gr),
-                                   p->grp_bits(p->yodd_mask, gr), p->tw, p->twlog, st) != 0)
-            return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
-    }
-    mark(p, GF_OP_ADJOINT, 2, st);
+    const size_t plane = (size_t)p->nx * p->ny;
+    char *R = (char *)workspace;
+    char *Gt = R + p->celem() * (size_t)Tc * rstride;
     gf::RowCombo ident{};
     ident.identity = 1;
     const double scale = kGrav / ((double)p->py * p->M);
     const gf::NyqSplit none{nullptr, 0, 0};
-    if (gf::launch_row_c2r(p->fp64(), p->px, Gt, (long)gstride, p->ngrp, p->nz, p->ny, p->ldc, p->nz, batch, ident,
-                           none, g, p->nx, scale, p->tw, p->twlog, st) != 0)
-        return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    mark(p, GF_OP_ADJOINT, 0, st);
+    for (int t0 = 0; t0 < p->nt; t0 += Tc) {
+        const int tc = std::min(Tc, p->nt - t0);
+        for (int j = 0; j < tc; ++j) {
+            const int t = t0 + j;
+            char *Rj = R + p->celem() * (size_t)j * rstride;
+            if (gf::launch_row_r2c(p->fp64(), p->px, (const char *)r + p->elem() * (size_t)t * p->n_out * plane, p->nx,
+                                   p->nx, p->ny, p->ldc, p->n_spec, p->nt * p->n_out, batch, p->in_combo, Rj, p->tw,
+                                   p->twlog, st) != 0)
+                return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
+            if (t == 0) mark(p, GF_OP_ADJOINT, 1, st);
+            for (int gr = 0; gr < p->ngrp; ++gr) {
+                const int c0 = p->grp_c0[gr];
+                if (gf::launch_col_adjoint(p->fp64(), p->py, Rj + p->celem() * (size_t)c0 * p->M * p->ldc,
+                                           p->spec_window(gr, t), Gt + p->celem() * (size_t)(j * p->ngrp + gr) * gstride,
+                                           batch, p->nz, p->M, p->ny, p->ldc, p->grp_cs[gr], p->n_spec, S, lps, nq,
+                                           p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr), p->tw,
+                                           p->twlog, st) != 0)
+                    return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+            }
+        }
+        if (t0 + tc == p->nt) mark(p, GF_OP_ADJOINT, 2, st);
+        if (gf::launch_row_c2r(p->fp64(), p->px, Gt, (long)gstride, tc * p->ngrp, p->nz, p->ny, p->ldc, p->nz, batch,
+                               ident, none, g, p->nx, scale, p->tw, p->twlog, st, 0, t0 > 0) != 0)
+            return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+    }
     mark(p, GF_OP_ADJOINT, 3, st);
     return GF_OK;
 }
@@ -701,7 +756,7 @@ gf_status gf_plan_last_pass_ms(gf_plan *p, int op, double ms[3])
 gf_status gf_debug_kernel_table(const gf_plan *p, int n, double *host_out)
 {
     if (!p || !host_out) return fail(GF_EINVAL, "NULL argument");
-    if (n < 0 || n >= p->nz) return fail(GF_EINVAL, "layer %d out of range", n);
+    if (n < 0 || n >= p->nzs) return fail(GF_EINVAL, "layer %d out of range", n);
     const size_t field = (size_t)p->py * p->px;
     DevBuf E;
     gf_status s;
@@ -732,7 +787,7 @@ gf_status gf_debug_kernel_table(const gf_plan *p, int n, double *host_out)
 gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double *host_out)
 {
     if (!p || !host_out) return fail(GF_EINVAL, "NULL argument");
-    if (n < 0 || n >= p->nz) return fail(GF_EINVAL, "layer %d out of range", n);
+    if (n < 0 || n >= p->nzs) return fail(GF_EINVAL, "layer %d out of range", n);
     int code = -1;
     for (int c = 0; c < gf::kMaxOut; ++c)
         if (c != 6 && component == (1u << c)) code = c;

@@ -262,7 +262,8 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     __attribute__((amdgpu_waves_per_eu(RowCfg<T, M>::WAVES_PER_EU)))
     row_c2r_kernel(const cx<T> *__restrict__ D, long split_stride, int nsplit, int nsrc, int rows, int ldc,
                    int nsub, long nrows_total, RowCombo cmb, const T *__restrict__ Dny, int nchunk,
-                   int nbatch, T *__restrict__ out, int nx_out, T sc, const cx<T> *__restrict__ tw, int twlog)
+                   int nbatch, T *__restrict__ out, long out_bstride, int accumulate, int nx_out, T sc,
+                   const cx<T> *__restrict__ tw, int twlog)
 {
     using C = RowCfg<T, M>;
     using F = typename C::FFT;
@@ -382,12 +383,24 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
     F::template run<true>(v, sre, sim, t, tw, twlog);
 
     if (gr < nrows_total) {
-        T *dst = out + gr * (long)nx_out;
+        // row (b, o, y) of the output; items of a batch are out_bstride apart
+        const long per_b = (long)nsub * rows;
+        const long bq = gr / per_b;
+        T *dst = out + bq * out_bstride + (gr - bq * per_b) * (long)nx_out;
+        if (accumulate) {
 #pragma unroll
-        for (int sl = 0; sl < PPT; ++sl) {
-            const unsigned j = t + NT * F::elem_out(sl);
-            if (2 * j < (unsigned)nx_out) dst[2 * j] = v[sl].re * sc;
-            if (2 * j + 1 < (unsigned)nx_out) dst[2 * j + 1] = v[sl].im * sc;
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_out(sl);
+                if (2 * j < (unsigned)nx_out) dst[2 * j] += v[sl].re * sc;
+                if (2 * j + 1 < (unsigned)nx_out) dst[2 * j + 1] += v[sl].im * sc;
+            }
+        } else {
+#pragma unroll
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_out(sl);
+                if (2 * j < (unsigned)nx_out) dst[2 * j] = v[sl].re * sc;
+                if (2 * j + 1 < (unsigned)nx_out) dst[2 * j + 1] = v[sl].im * sc;
+            }
         }
     }
 }
@@ -411,8 +424,8 @@ static int run_r2c(const void *in, long row_len, int lin, int rows, int ldc, int
 
 template <typename T, int M>
 static int run_c2r(const void *D, long split_stride, int nsplit, int nsrc, int rows, int ldc, int nsub,
-                   int nbatch, const RowCombo &cmb, const NyqSplit &nq, void *out, int nx_out, double scale_,
-                   const void *tw, int twlog, hipStream_t st)
+                   int nbatch, const RowCombo &cmb, const NyqSplit &nq, void *out, long out_bstride, bool accumulate,
+                   int nx_out, double scale_, const void *tw, int twlog, hipStream_t st)
 {
     using C = RowCfg<T, M>;
     const long nrows = (long)nbatch * nsub * rows;
@@ -422,8 +435,9 @@ static int run_c2r(const void *D, long split_stride, int nsplit, int nsrc, int r
     if (lds > lds_limit()) return -3;
     hipLaunchKernelGGL((row_c2r_kernel<T, M>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
                        (const cx<T> *)D, split_stride, nsplit, nsrc, rows, ldc, nsub, nrows, cmb,
-                       (const T *)nq.Dny, nq.Dny ? nq.Sny : 0, nbatch, (T *)out, nx_out, (T)scale_,
-                       (const cx<T> *)tw, twlog);
+                       (const T *)nq.Dny, nq.Dny ? nq.Sny : 0, nbatch, (T *)out,
+                       out_bstride > 0 ? out_bstride : (long)nsub * rows * nx_out, accumulate ? 1 : 0, nx_out,
+                       (T)scale_, (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -450,15 +464,16 @@ int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int
 
 int launch_row_c2r(bool fp64, int px, const void *D, long split_stride, int nsplit, int nsrc,
                    int rows, int ldc, int nsub, int nbatch, const RowCombo &cmb, const NyqSplit &nq,
-                   void *out, int nx_out, double scale_, const void *tw, int twlog, hipStream_t st)
+                   void *out, int nx_out, double scale_, const void *tw, int twlog, hipStream_t st,
+                   long out_bstride, bool accumulate)
 {
     const int M = px / 2;
 #define CASE(MM)                                                                              \
     case MM:                                                                                  \
         return fp64 ? run_c2r<double, MM>(D, split_stride, nsplit, nsrc, rows, ldc, nsub, nbatch, cmb, \
-                                          nq, out, nx_out, scale_, tw, twlog, st)             \
+                                          nq, out, out_bstride, accumulate, nx_out, scale_, tw, twlog, st) \
                     : run_c2r<float, MM>(D, split_stride, nsplit, nsrc, rows, ldc, nsub, nbatch, cmb,  \
-                                         nq, out, nx_out, scale_, tw, twlog, st);
+                                         nq, out, out_bstride, accumulate, nx_out, scale_, tw, twlog, st);
     switch (M) {
         GF_ROW_SIZES(CASE)
     default:

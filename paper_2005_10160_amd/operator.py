@@ -39,7 +39,7 @@ class Plan:
     """A geometry's resident kernel spectra (see include/gravfft.h)."""
 
     def __init__(self, nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64",
-                 max_batch=0, device=None, stream=None, zedges=None):
+                 max_batch=0, device=None, stream=None, zedges=None, levels=1):
         lib = nat.load()
         device = torch.device("cuda") if device is None else torch.device(device)
         if device.type != "cuda":
@@ -57,7 +57,14 @@ class Plan:
         handle = ctypes.c_void_p()
         with torch.cuda.device(self.device):
             st = _stream_handle(stream)
-            if zedges is None:
+            if zedges is not None and int(levels) != 1:
+                raise ValueError("observation levels need uniform layers")
+            if int(levels) != 1:
+                nat.check(lib.gf_plan_create_levels(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz),
+                                                    float(h), int(levels), ctypes.c_uint(self.mask), prec,
+                                                    int(max_batch), st, ctypes.byref(handle)),
+                          "gf_plan_create_levels")
+            elif zedges is None:
                 nat.check(lib.gf_plan_create(int(nx), int(ny), int(nz), float(dx), float(dy), float(dz), float(h),
                                              ctypes.c_uint(self.mask), prec, int(max_batch), st,
                                              ctypes.byref(handle)),
@@ -77,6 +84,9 @@ class Plan:
         self.info = info
         self.nx, self.ny, self.nz = info.nx, info.ny, info.nz
         self.n_out = info.n_out
+        self.n_levels = info.n_levels
+        # one data plane per observation level
+        self.data_shape = ((self.n_levels,) if self.n_levels > 1 else ()) + (self.n_out, self.ny, self.nx)
         self.out_components = tuple(COMPONENTS[i] for i in range(len(COMPONENTS)) if self.mask >> i & 1)
 
     # -- lifetime ---------------------------------------------------------
@@ -140,13 +150,14 @@ class Plan:
 
     # -- operator ----------------------------------------------------------
     def forward(self, rho, out=None, workspace=None, stream=None):
-        """d = G rho.  rho [B][nz][ny][nx] (or [nz][ny][nx]) -> d [B][C][ny][nx]."""
+        """d = G rho.  rho [B][nz][ny][nx] (or [nz][ny][nx]) -> d [B][C][ny][nx]
+        ([B][levels][C][ny][nx] for a plan of several observation levels)."""
         squeeze = rho.dim() == 3
         rho = self._check_in(rho, (self.nz, self.ny, self.nx), "rho")
         B = rho.shape[0]
         if out is None:
-            out = torch.empty((B, self.n_out, self.ny, self.nx), dtype=self.dtype, device=self.device)
-        out = self._check_in(out, (self.n_out, self.ny, self.nx), "d")
+            out = torch.empty((B,) + self.data_shape, dtype=self.dtype, device=self.device)
+        out = self._check_in(out, self.data_shape, "d")
         if out.shape[0] != B:
             raise ValueError("d batch %d != rho batch %d" % (out.shape[0], B))
         ws, nb = self._workspace("forward", B, workspace, stream)
@@ -157,9 +168,10 @@ class Plan:
         return out[0] if squeeze else out
 
     def adjoint(self, r, out=None, workspace=None, stream=None):
-        """g = G^T r.  r [B][C][ny][nx] (or [C][ny][nx]) -> g [B][nz][ny][nx]."""
-        squeeze = r.dim() == 3
-        r = self._check_in(r, (self.n_out, self.ny, self.nx), "r")
+        """g = G^T r.  r [B][C][ny][nx] (or [C][ny][nx]; with levels
+        [B][levels][C][ny][nx]) -> g [B][nz][ny][nx]."""
+        squeeze = r.dim() == len(self.data_shape)
+        r = self._check_in(r, self.data_shape, "r")
         B = r.shape[0]
         if out is None:
             out = torch.empty((B, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
@@ -205,6 +217,14 @@ class Plan:
 
 def plan(nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64", max_batch=0, device=None, stream=None):
     return Plan(nx, ny, nz, dx, dy, dz, h, components, precision, max_batch, device, stream)
+
+
+def plan_levels(nx, ny, nz, dx, dy, dz, h, levels, components=ALL6, precision="f64", max_batch=0, device=None,
+                stream=None):
+    """Plan of the equal-dimension survey: stations on `levels` planes at
+    heights h + t dz (t = 0 .. levels-1) above the model top; data
+    [B][levels][C][ny][nx]."""
+    return Plan(nx, ny, nz, dx, dy, dz, h, components, precision, max_batch, device, stream, levels=levels)
 
 
 def plan_layered(nx, ny, dx, dy, zedges, h, components=ALL6, precision="f64", max_batch=0, device=None,

@@ -103,3 +103,13 @@ def test_layered_plan_rejects_bad_edges(lib, edges, what):
     assert st == _native.GF_EINVAL, what
     assert h.value is None
     assert lib.gf_last_error().decode() != ""
+
+
+@pytest.mark.parametrize("levels,dz,what", [(0, 50.0, "no level"), (-3, 50.0, "negative"), (4, 0.0, "dz")])
+def test_levels_plan_rejects_bad_arguments(lib, levels, dz, what):
+    from paper_2005_10160_amd import _native
+    h = ctypes.c_void_p(123)
+    st = lib.gf_plan_create_levels(16, 16, 4, 50.0, 50.0, dz, 25.0, levels, ctypes.c_uint(0x3F), 0, 0, None,
+                                   ctypes.byref(h))
+    assert st == _native.GF_EINVAL, what
+    assert h.value is None

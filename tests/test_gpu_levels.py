@@ -1,0 +1,131 @@
+"""GPU parity of the equal-dimension survey (section 2.2, Fig. 2a): stations
+on several planes dz apart above the model (gf_plan_create_levels), against
+the CPU oracle's per-level direct sums.
+
+Bar as for a single plane: relative L2 <= 1e-10 per component and level in
+FP64, <= 1e-5 in FP32.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from synth import Geometry, PRESETS, tiny_density, prisms_and_grf, sample_stations
+
+pytestmark = pytest.mark.gpu
+
+ALL9 = 0x1FF
+NAMES = ("gz", "gxx", "gxy", "gxz", "gyy", "gyz", "gzz", "gx", "gy")
+TOL = {"f64": 1e-10, "f32": 1e-5}
+DOT = {"f64": 1e-13, "f32": 1e-6}
+
+
+def note(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_10160_amd as gf
+    from paper_2005_10160_amd import _native
+    _native.load()
+    return gf
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def grid(orc_out, g):
+    """(levels, nst, C) in station row order -> (levels, C, ny, nx)."""
+    L = orc_out.shape[0]
+    return orc_out.reshape(L, g.ny, g.nx, -1).transpose(0, 3, 1, 2)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("geom,levels", [
+    (Geometry(12, 10, 6, 20.0, 30.0, 15.0, 9.0), 6),     # equal dimension: as many levels as layers
+    (Geometry(13, 7, 3, 17.0, 23.0, 11.0, 5.0), 5),      # more levels than layers, two adjoint chunks
+    (Geometry(20, 12, 5, 30.0, 20.0, 10.0, 8.0), 2),
+])
+def test_levels_forward_adjoint(gf, orc, geom, levels, prec):
+    note("levels %s x %d %s" % (geom, levels, prec))
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rho = tiny_density(geom.nx, geom.ny, geom.nz, seed=51, block=None)
+    p = gf.plan_levels(geom.nx, geom.ny, geom.nz, geom.dx, geom.dy, geom.dz, geom.h, levels, ALL9, prec)
+    assert p.n_levels == levels and p.data_shape == (levels, 9, geom.ny, geom.nx)
+    d = p.forward(torch.from_numpy(rho).to("cuda", dt)).double().cpu().numpy()
+    want = grid(orc.forward_levels(geom, rho, levels), geom)
+    for t in range(levels):
+        for c in range(len(NAMES)):
+            e = rel(d[t, c], want[t, c])
+            assert e <= TOL[prec], (t, NAMES[c], e)
+    rng = np.random.default_rng(52)
+    r = rng.standard_normal((levels, len(NAMES), geom.ny, geom.nx))
+    g_out = p.adjoint(torch.from_numpy(r).to("cuda", dt)).double().cpu().numpy()
+    wa = orc.adjoint_levels(geom, r, ALL9, levels)
+    assert rel(g_out, wa) <= TOL[prec]
+    lhs = float(np.sum(d * r))
+    rhs = float(np.sum(rho * g_out))
+    assert abs(lhs - rhs) <= DOT[prec] * np.linalg.norm(d) * np.linalg.norm(r), (lhs, rhs)
+    p.close()
+
+
+def test_levels_batch_equals_single(gf):
+    """Batched models interleave with the levels in d ([B][levels][C]...):
+    every model's result is bitwise its result alone, forward and adjoint
+    (five levels: two adjoint chunks, the second added to the first)."""
+    g = Geometry(24, 16, 6, 20.0, 20.0, 20.0, 10.0)
+    levels = 5
+    rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (1, 2, 3)])
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, 0x181, "f64")
+    both = p.forward(torch.from_numpy(rho).cuda()).cpu().numpy()
+    assert both.shape == (3, levels, 3, g.ny, g.nx)
+    for b in range(3):
+        one = p.forward(torch.from_numpy(rho[b]).cuda()).cpu().numpy()
+        assert np.array_equal(both[b], one), b
+    r = np.random.default_rng(53).standard_normal(both.shape)
+    gt = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy()
+    for b in range(3):
+        one = p.adjoint(torch.from_numpy(r[b]).cuda()).cpu().numpy()
+        assert np.array_equal(gt[b], one), b
+    p.close()
+
+
+def test_one_level_is_the_single_plane(gf):
+    g = Geometry(40, 30, 12, 20.0, 20.0, 20.0, 10.0)
+    rho = torch.from_numpy(tiny_density(g.nx, g.ny, g.nz, seed=54, block=None)).cuda()
+    p1 = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, "f64")
+    pl = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 1, ALL9, "f64")
+    assert torch.equal(p1.forward(rho), pl.forward(rho))
+    r = torch.randn((9, g.ny, g.nx), dtype=torch.float64, generator=torch.Generator().manual_seed(5)).cuda()
+    assert torch.equal(p1.adjoint(r), pl.adjoint(r))
+    p1.close()
+    pl.close()
+
+
+def test_levels_medium_sampled(gf, orc):
+    """256x256x64 with 64 levels (equal dimension), 25x25x20 m cells,
+    h = 10 m, prisms plus a random field: sampled stations on the lowest,
+    a middle and the highest level against the direct sum."""
+    g = PRESETS["medium"]
+    levels = g.nz
+    rho = prisms_and_grf(g.nx, g.ny, g.nz, 6, 202, 203)
+    note("levels medium: forward (%d levels)" % levels)
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, 0x3F, "f64")
+    d = p.forward(torch.from_numpy(rho).cuda()).cpu().numpy()
+    p.close()
+    st = sample_stations(g.nx, g.ny, 3, seed=55)
+    for t in (0, levels // 2, levels - 1):
+        note("levels medium: oracle at level %d, %d stations" % (t, len(st)))
+        gt = Geometry(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz)
+        want = orc.forward(gt, rho, st)
+        for c in range(6):
+            gv = d[t, c][st[:, 1], st[:, 0]]
+            e = rel(gv, want[:, c])
+            assert e <= TOL["f64"], (t, NAMES[c], e)

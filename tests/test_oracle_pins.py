@@ -428,3 +428,41 @@ def test_layered_offset_table_is_a_shifted_uniform_layer(orc):
             for c in range(orc.NCOMP):
                 s = np.abs(want[c]).max()
                 assert np.abs(got[c] - want[c]).max() <= 1e-14 * s, (n, mode, c)
+
+
+# --------------------------------------------------------------- pin 14 ----
+def test_levels_are_translation_equivalent_in_depth(orc):
+    """Eq. 10 for the equal-dimension survey: with station levels dz apart,
+    the block of level t and layer n is the block of level 0 and layer
+    n + t (the same prism seen from the same relative position)."""
+    g = Geometry(9, 7, 6, 20.0, 30.0, 15.0, 7.0)
+    for t in (1, 2, 5):
+        gt = Geometry(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz)
+        for n in range(g.nz - t):
+            a = orc.kernel_table(gt, n)
+            b = orc.kernel_table(g, n + t)
+            for c in range(orc.NCOMP):
+                s = np.abs(b[c]).max()
+                assert np.abs(a[c] - b[c]).max() <= 1e-14 * s, (t, n, c)
+
+
+def test_levels_forward_and_adjoint_compose(orc):
+    """The multi-level operator stacks the single-plane operators of each
+    level, and its adjoint sums theirs: the dot-product identity over all
+    levels and components."""
+    g = Geometry(6, 5, 3, 20.0, 25.0, 15.0, 9.0)
+    levels = 4
+    rng = np.random.default_rng(61)
+    m = rng.standard_normal((g.nz, g.ny, g.nx)) * 300
+    d = orc.forward_levels(g, m, levels)                       # (levels, nst, NCOMP)
+    assert d.shape == (levels, g.nx * g.ny, orc.NCOMP)
+    r = rng.standard_normal((levels, orc.NCOMP, g.ny, g.nx))
+    comps = [0, 1, 2, 3, 4, 5, 7, 8]
+    mask = sum(1 << c for c in comps)
+    gt = orc.adjoint_levels(g, r, mask, levels)
+    dg = d.reshape(levels, g.ny, g.nx, orc.NCOMP).transpose(0, 3, 1, 2)
+    lhs = sum(np.vdot(dg[t, c], r[t, c]) for t in range(levels) for c in comps)
+    rhs = np.vdot(m, gt)
+    assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(dg[:, comps]) * np.linalg.norm(r[:, comps])
+    # level 0 is the single plane
+    assert np.array_equal(d[0], orc.forward(g, m))
