@@ -16,6 +16,7 @@ FP32 path, the adjoint, a live roofline of the dominant kernel (the column
 pass) with the device's practical copy and read rates beside the 8 TB/s
 peak, the same model with other component sets (gz with the first
 derivatives gx, gy; all nine outputs) and on a depth-stretched layered mesh,
+the equal-dimension survey (as many observation levels as layers),
 the batched inversion-step workload (512^2 x 128, 32 models, forward
 and adjoint in both precisions), the CPU oracle timed on a bounded sample,
 and a served-latency run:
@@ -291,18 +292,21 @@ def main():
     log("bench: generating density %dx%dx%d" % (g.nx, g.ny, g.nz))
     rho_np = prisms_and_grf(g.nx, g.ny, g.nz, 20 if not args.small else 6, 302, 303)
 
-    def run(prec, steps, warmup, with_adjoint, mask=gf.ALL6, zedges=None):
+    def run(prec, steps, warmup, with_adjoint, mask=gf.ALL6, zedges=None, levels=1):
         dt = torch.float64 if prec == "f64" else torch.float32
-        log("bench: plan %s, components 0x%x%s" % (prec, mask, "" if zedges is None else ", layered"))
+        log("bench: plan %s, components 0x%x%s%s" % (prec, mask, "" if zedges is None else ", layered",
+                                                    "" if levels == 1 else ", %d levels" % levels))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        if zedges is None:
+        if levels != 1:
+            p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, mask, prec, device=dev)
+        elif zedges is None:
             p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, prec, device=dev)
         else:
             p = gf.plan_layered(g.nx, g.ny, g.dx, g.dy, zedges, g.h, mask, prec, device=dev)
         plan_wall = (time.perf_counter() - t0) * 1e3
         rho = torch.from_numpy(rho_np).to(dev, dt)
-        d = torch.empty((1, p.n_out, g.ny, g.nx), dtype=dt, device=dev)
+        d = torch.empty((1,) + p.data_shape, dtype=dt, device=dev)
         wsb = max(p.workspace_bytes("forward", 1), p.workspace_bytes("adjoint", 1))
         ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
         log("bench: timing %s forward" % prec)
@@ -434,6 +438,23 @@ def main():
                 r["plan"].close()
                 del r
         line["component_sets"] = sets
+
+        # the equal-dimension survey: as many observation levels as layers
+        # (stations on 100 planes 20 m apart above the model), six
+        # components; each level is a column pass over its window of the
+        # 199 resident layer spectra
+        lev = {"levels": g.nz, "workload": "equal-dimension survey, %dx%dx%d model, %d observation levels, "
+                                           "6 components, batch 1" % (g.nx, g.ny, g.nz, g.nz)}
+        for prec in ("f64", "f32"):
+            r = run(prec, 3, 1, True, gf.ALL6, None, g.nz)
+            ms = sum(r["per"]) / len(r["per"])
+            evals_l = 6.0 * g.nz * g.nd * g.nm
+            lev[prec] = {"ms_per_step": round(ms, 3), "effective_evals_per_s": evals_l / (ms * 1e-3),
+                         "adjoint_ms": round(r["adjoint_ms"], 3), "plan_ms": round(r["plan_ms"], 1),
+                         "spectra_bytes": r["spectra_bytes"]}
+            r["plan"].close()
+            del r
+        line["levels"] = lev
 
     if not args.no_batched and not args.small:
         line["batched"] = batched_step(5, 1)
