@@ -93,6 +93,16 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
                        int nz, int M, int ny, int ldc, int Cs, int Ct, int nsplit, int lps, const NyqSplit &nq,
                        unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 
+// Forward column pass of nlev observation levels at once for Cs <= 3
+// spectra (nlev * Cs <= 6): level j sums spectral layers n + j from `spec`
+// over model layers n; D and nq.Dny hold nlev * Cs slots (level-major).
+// Only for transform lengths that run in the wave split
+// (col_levels_blocked).
+int launch_col_forward_levels(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz, int M,
+                              int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
+                              unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
+bool col_levels_blocked(int py);
+
 // Plan time: column FFT of the row-transformed kernel fields and extraction
 // of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).
 int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,

@@ -150,6 +150,13 @@ struct gf_plan {
     // levels per chunk of the adjoint (each level of a chunk has its own
     // residual spectra and layer columns; the inverse rows sum the chunk)
     int adj_chunk() const { return std::min(nt, 4); }
+    // Forward of several levels per column pass (one density transform per
+    // layer for all of them, spectral layers in an LDS ring): plans of up to
+    // three spectra at wave-split transform lengths
+    bool levels_blocked() const { return nt > 1 && n_spec <= 3 && gf::col_levels_blocked(py); }
+    int levels_per_pass() const { return levels_blocked() ? std::min(nt, 6 / n_spec) : 1; }
+    // slots of the forward column pass's outputs (D and Dny)
+    int fwd_slots() const { return levels_per_pass() * n_spec; }
     unsigned grp_bits(unsigned m, int g) const { return (m >> grp_c0[g]) & ((1u << grp_cs[g]) - 1u); }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
     size_t celem() const { return 2 * elem(); }
@@ -188,7 +195,7 @@ struct gf_plan {
     {
         int Sny, l;
         nyq_split(&Sny, &l);
-        return elem() * (size_t)Sny * B * n_spec * ldc;
+        return elem() * (size_t)Sny * B * fwd_slots() * ldc;
     }
     void fwd_split(int /*B*/, int *S, int *lps) const
     {
@@ -232,7 +239,7 @@ struct gf_plan {
         if (op == GF_OP_FORWARD) {
             int S, l;
             fwd_split(B, &S, &l);
-            return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * n_spec) + nyq_bytes(B);
+            return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * fwd_slots()) + nyq_bytes(B);
         }
         return celem() * (size_t)M * ldc * (size_t)adj_chunk() * ((size_t)B * n_spec + (size_t)ngrp * B * nz);
     }
@@ -633,7 +640,7 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
     char *D = R + p->celem() * (size_t)batch * p->nz * p->M * p->ldc;
     gf::NyqSplit nq{nullptr, 0, 0};
     p->nyq_split(&nq.Sny, &nq.lps_ny);
-    if (nq.Sny > 0) nq.Dny = D + p->celem() * (size_t)S * batch * p->n_spec * p->M * p->ldc;
+    if (nq.Sny > 0) nq.Dny = D + p->celem() * (size_t)S * batch * p->fwd_slots() * p->M * p->ldc;
     gf::RowCombo ident{};
     ident.identity = 1;
     mark(p, GF_OP_FORWARD, 0, st);
@@ -646,6 +653,32 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
     const size_t plane = (size_t)p->nx * p->ny;
     const long dstride = (long)p->nt * p->n_out * (long)plane;
     const double scale = kGrav / ((double)p->py * p->M);
+    if (p->levels_blocked()) {
+        // passes of up to levels_per_pass() levels; level j of a pass is
+        // slots [j Cs, (j+1) Cs) of its D and Dny
+        const int per = p->levels_per_pass();
+        for (int t0 = 0; t0 < p->nt; t0 += per) {
+            const int nlev = std::min(per, p->nt - t0);
+            const int slots = nlev * p->n_spec;
+            if (gf::launch_col_forward_levels(p->fp64(), p->py, R, p->spec_window(0, t0), D, batch, p->nz, p->M, p->ny,
+                                              p->ldc, p->n_spec, nlev, S, lps, nq, p->imag_mask, p->yodd_mask, p->tw,
+                                              p->twlog, st) != 0)
+                return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+            if (t0 + nlev == p->nt) mark(p, GF_OP_FORWARD, 2, st);
+            for (int j = 0; j < nlev; ++j) {
+                gf::RowCombo cmb = p->out_combo;
+                for (int o = 0; o < p->n_out; ++o)
+                    for (int i = 0; i < cmb.nterm[o]; ++i) cmb.src[o][i] += j * p->n_spec;
+                if (gf::launch_row_c2r(p->fp64(), p->px, D, (long)batch * slots * p->M * p->ldc, S, slots, p->ny,
+                                       p->ldc, p->n_out, batch, cmb, nq,
+                                       (char *)d + p->elem() * (size_t)(t0 + j) * p->n_out * plane, p->nx, scale,
+                                       p->tw, p->twlog, st, dstride, false) != 0)
+                    return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+            }
+        }
+        mark(p, GF_OP_FORWARD, 3, st);
+        return GF_OK;
+    }
     for (int t = 0; t < p->nt; ++t) {
         for (int gr = 0; gr < p->ngrp; ++gr) {
             const int c0 = p->grp_c0[gr];

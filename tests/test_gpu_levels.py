@@ -109,23 +109,63 @@ def test_one_level_is_the_single_plane(gf):
     pl.close()
 
 
-def test_levels_medium_sampled(gf, orc):
+@pytest.mark.parametrize("mask", [0x3F, 0x1])
+def test_levels_medium_sampled(gf, orc, mask):
     """256x256x64 with 64 levels (equal dimension), 25x25x20 m cells,
     h = 10 m, prisms plus a random field: sampled stations on the lowest,
-    a middle and the highest level against the direct sum."""
+    a middle and the highest level against the direct sum (gz alone runs
+    six levels per column pass)."""
     g = PRESETS["medium"]
     levels = g.nz
     rho = prisms_and_grf(g.nx, g.ny, g.nz, 6, 202, 203)
-    note("levels medium: forward (%d levels)" % levels)
-    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, 0x3F, "f64")
+    note("levels medium: forward (%d levels, components 0x%x)" % (levels, mask))
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, mask, "f64")
     d = p.forward(torch.from_numpy(rho).cuda()).cpu().numpy()
     p.close()
+    comps = [c for c in range(9) if mask >> c & 1]
     st = sample_stations(g.nx, g.ny, 3, seed=55)
     for t in (0, levels // 2, levels - 1):
         note("levels medium: oracle at level %d, %d stations" % (t, len(st)))
         gt = Geometry(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz)
         want = orc.forward(gt, rho, st)
-        for c in range(6):
-            gv = d[t, c][st[:, 1], st[:, 0]]
+        for i, c in enumerate(comps):
+            gv = d[t, i][st[:, 1], st[:, 0]]
             e = rel(gv, want[:, c])
             assert e <= TOL["f64"], (t, NAMES[c], e)
+
+
+# several levels per column pass (plans of one to three spectra at column
+# lengths >= 256): gz alone (six levels a pass, here passes of 6 and 3), gz
+# with gx and gy (two a pass), gz with gzz (three spectra, gzz from two)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("mask", [0x1, 0x181, 0x41])
+def test_levels_blocked_passes(gf, orc, mask, prec):
+    """Every level of every station against single-plane plans at the
+    level's height (the same operator through the one-level kernels), a
+    sample against the oracle, and batch = single bitwise."""
+    g = Geometry(40, 130, 7, 20.0, 25.0, 15.0, 7.0)
+    levels = 9
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (56, 57)])
+    note("blocked levels %s mask 0x%x %s" % (g, mask, prec))
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, mask, prec)
+    x = torch.from_numpy(rho).to("cuda", dt)
+    d = p.forward(x).double().cpu().numpy()
+    for b in range(2):
+        one = p.forward(x[b]).double().cpu().numpy()
+        assert np.array_equal(d[b], one), b
+    close = 1e-12 if prec == "f64" else 1e-6
+    for t in range(levels):
+        q = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz, mask, prec)
+        want = q.forward(x).double().cpu().numpy()
+        q.close()
+        for c in range(want.shape[1]):
+            assert rel(d[:, t, c], want[:, c]) <= close, (t, c)
+    comps = [c for c in range(9) if mask >> c & 1]
+    st = np.array([(0, 0), (g.nx - 1, g.ny - 1), (g.nx // 2, g.ny // 2), (g.nx // 3, (2 * g.ny) // 3)])
+    want = orc.forward_levels(g, rho[1], levels, st)          # (levels, nst, NCOMP)
+    for t in (0, 4, levels - 1):
+        for i, c in enumerate(comps):
+            e = rel(d[1, t, i][st[:, 1], st[:, 0]], want[t, :, c])
+            assert e <= TOL[prec], (t, NAMES[c], e)
+    p.close()
