@@ -1098,6 +1098,119 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
 }
 
+// Adjoint column pass of several observation levels at once (plans of up
+// to three spectra): the nlev * Cs residual columns of the pass's levels
+// (R slot k = j * Cs + c: level j, spectrum c) are transformed once; per
+// model layer n, sum_{j,c} K^_{c,n+j} r^_{j,c} is inverse-transformed into
+// Gout column n.  Spectral layers form a ring of nlev + 1 in LDS as in the
+// forward levels pass.
+template <typename T, int N>
+__global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(WsCfg<T, N>::WAVES_PER_EU)))
+    col_levels_adjoint_ws_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec, cx<T> *__restrict__ Gout,
+                                 int B, int nz, int M, int ny, int ldc, int Cs, int nlev, int lps, int nblk_ny,
+                                 int Sny, int lps_ny, int nblk_main, unsigned imag_mask, unsigned yodd_mask,
+                                 const cx<T> *__restrict__ tw, int twlog)
+{
+    using C = WsCfg<T, N>;
+    using F = typename C::FFT;
+    constexpr int CMAX = 6;
+    constexpr int PPT = C::PPT, L = C::L, NW = C::NW, G = C::G, GT = C::GT, QP = C::QP;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned g = wv / NW, w = wv % NW;
+    const unsigned tg = threadIdx.x - g * GT;
+    T *twq = lds;
+    T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
+    T *sbuf = gb;                                                        // ring: (nlev + 1) x Cs x QP <= 2 x CMAX x QP
+    T *cre = gb + 2 * CMAX * QP;                                         // combination: 2N words
+    cx<T> *rbuf = reinterpret_cast<cx<T> *>(gb);                         // residual columns (setup only)
+    T *xch = gb + 2 * CMAX * QP + 2 * C::CW + w * C::XW;
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
+    F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
+
+    WsTwiddles<T, N, PPT> tws;
+    cx<T> cn[NW > 1 ? NW / 2 : 1];
+    if constexpr (NW > 1) {
+        tws.init(tw, twlog, lane, w);
+        constexpr int LOGN = ilog2<N>::value;
+#pragma unroll
+        for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
+    }
+    unsigned lo, hi;
+    ws_offsets<NW, L>(w, lo, hi);
+
+    const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
+    const unsigned row = spec_row(un.uv, (unsigned)M);
+    const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
+    const unsigned rowvals = (unsigned)Cs * QP;
+    const int ring = nlev + 1;
+    const int nk = nlev * Cs;
+    const int n0 = un.n0;
+    const int n1 = un.n1;
+
+    // residual columns into the spectrum area (nk x N/2 complex fit in 2 x CMAX x QP words)
+#pragma unroll
+    for (int k = 0; k < CMAX; ++k) {
+        if (k < nk) {
+            for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) rbuf[k * (N / 2) + i] = cx<T>{T(0), T(0)};
+            cx<T> tail{T(0), T(0)};
+            stage_column<T, GT>(column(R, (size_t)un.b * nk + k, M, un.u, ldc), rbuf + k * (N / 2), ny, tg, tail);
+            put_tail(rbuf + k * (N / 2), ny, tg, tail);
+        }
+    }
+    stage_wait<true>();
+    cx<T> rh[CMAX][PPT];
+#pragma unroll
+    for (int k = 0; k < CMAX; ++k) {
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) rh[k][s] = cx<T>{T(0), T(0)};
+        if (k < nk) {
+            const cx<T> *xc = rbuf + k * (N / 2);
+            if (un.part == 0)
+                form_z<F, T, N, NW, L, PPT, 0>(rh[k], xc, lane, w, cn, tws);
+            else if (un.part == 1)
+                form_z<F, T, N, NW, L, PPT, 1>(rh[k], xc, lane, w, cn, tws);
+            else
+                form_z<F, T, N, NW, L, PPT, 2>(rh[k], xc, lane, w, cn, tws);
+            F::template run<false>(rh[k], xch, nullptr, lane, twp, twlog);
+        }
+    }
+    lds_barrier();   // every wave is past its reads of the residual columns
+
+    auto stage_spec = [&](int sl) {
+        stage_rows<T, GT, true>(spec + (size_t)sl * layer_vals + (size_t)row * rowvals,
+                                sbuf + (size_t)(sl % ring) * rowvals, rowvals, tg);
+    };
+    if (n0 < n1)
+        for (int j = 0; j < nlev; ++j) stage_spec(n0 + j);
+    stage_wait<true>();
+
+    for (int n = n0; n < n1; ++n) {
+        if (n + 1 < n1) stage_spec(n + nlev);
+        cx<T> v[PPT];
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) v[s] = cx<T>{T(0), T(0)};
+#pragma unroll
+        for (int k = 0; k < CMAX; ++k)
+            if (k < nk) {
+                const int j = k / Cs, c = k - j * Cs;
+                const T *srow = sbuf + (size_t)((n + j) % ring) * rowvals + (size_t)c * QP;
+                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[k], srow, lane, lo, hi, (imag_mask >> c) & 1u,
+                                                     (yodd_mask >> c) & 1u);
+            }
+        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre);
+        lds_barrier();
+        if (un.active)
+            ws_store<T, N, NW, L, PPT, GT>(cre, Gout + (((size_t)un.b * nz + n) * M + un.u) * (size_t)ldc, tg, ny,
+                                           un.part);
+        stage_wait<true>();
+    }
+}
+
 // Plan time: full-length column FFT of the row-transformed kernel fields
 // (double), keeping one real per frequency of the quarter plane.  Virtual
 // units as in the adjoint.
@@ -1238,6 +1351,28 @@ static int run_levels(const void *R, const void *spec, void *D, int B, int nz, i
     }
 }
 
+template <typename T, int N>
+static int run_levels_adj(const void *R, const void *spec, void *Gout, int B, int nz, int M, int ny, int ldc, int Cs,
+                          int nlev, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
+                          const void *tw, int twlog, hipStream_t st)
+{
+    if constexpr (use_ws<N>()) {
+        using C = WsCfg<T, N>;
+        const long nblk_main = ((long)M * B + C::G - 1) / C::G;
+        const long nblk_ny = (long)nq.Sny * ((B + C::G - 1) / C::G);
+        const size_t lds = C::lds_bytes(6);
+        if (lds > lds_limit()) return -3;
+        if (nq.Sny < 1 || nq.lps_ny < 1) return -2;
+        hipLaunchKernelGGL((col_levels_adjoint_ws_kernel<T, N>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
+                           dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)Gout, B, nz, M,
+                           ny, ldc, Cs, nlev, lps, (int)nblk_ny, nq.Sny, nq.lps_ny, (int)nblk_main, imag_mask,
+                           yodd_mask, (const cx<T> *)tw, twlog);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    } else {
+        return -2;
+    }
+}
+
 template <typename TO, int N>
 static int run_kgen(const void *Rk, void *spec, int nl, int n0, int Cs, int nz, int M,
                     unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
@@ -1339,6 +1474,25 @@ int launch_col_forward_levels(bool fp64, int py, const void *R, const void *spec
                                              yodd_mask, tw, twlog, st)                                       \
                     : run_levels<float, NN>(R, spec, D, B, nz, M, ny, ldc, Cs, nlev, nsplit, lps, nq, imag_mask,  \
                                             yodd_mask, tw, twlog, st);
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return -2;
+    }
+#undef CASE
+}
+
+int launch_col_adjoint_levels(bool fp64, int py, const void *R, const void *spec, void *Gout, int B, int nz, int M,
+                              int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
+                              unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st)
+{
+    if (Cs < 1 || nlev < 1 || nlev * Cs > 6 || (nlev + 1) * Cs > 12 || ny < 1 || 2 * ny > py || ldc < ny) return -2;
+#define CASE(NN)                                                                                                 \
+    case NN:                                                                                                     \
+        return fp64 ? run_levels_adj<double, NN>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nlev, nsplit, lps, nq,      \
+                                                 imag_mask, yodd_mask, tw, twlog, st)                            \
+                    : run_levels_adj<float, NN>(R, spec, Gout, B, nz, M, ny, ldc, Cs, nlev, nsplit, lps, nq,       \
+                                                imag_mask, yodd_mask, tw, twlog, st);
     switch (py) {
         GF_COL_SIZES(CASE)
     default:

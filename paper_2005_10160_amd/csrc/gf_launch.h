@@ -101,6 +101,11 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
 int launch_col_forward_levels(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz, int M,
                               int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
                               unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
+// Adjoint column pass of nlev observation levels at once: R holds the
+// pass's nlev * Cs residual slots (level-major), Gout one layer-column slab.
+int launch_col_adjoint_levels(bool fp64, int py, const void *R, const void *spec, void *Gout, int B, int nz, int M,
+                              int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
+                              unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 bool col_levels_blocked(int py);
 
 // Plan time: column FFT of the row-transformed kernel fields and extraction

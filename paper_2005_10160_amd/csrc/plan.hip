@@ -147,9 +147,10 @@ struct gf_plan {
     {
         return spec_group(g) + elem() * (size_t)t * U * grp_cs[g] * QP;
     }
-    // levels per chunk of the adjoint (each level of a chunk has its own
-    // residual spectra and layer columns; the inverse rows sum the chunk)
-    int adj_chunk() const { return std::min(nt, 4); }
+    // column passes per chunk of the adjoint (each pass of a chunk has its
+    // own residual spectra and layer columns; the inverse rows sum the chunk)
+    int adj_passes() const { return (nt + levels_per_pass() - 1) / levels_per_pass(); }
+    int adj_chunk() const { return std::min(adj_passes(), 4); }
     // Forward of several levels per column pass (one density transform per
     // layer for all of them, spectral layers in an LDS ring): plans of up to
     // three spectra at wave-split transform lengths
@@ -241,7 +242,7 @@ struct gf_plan {
             fwd_split(B, &S, &l);
             return celem() * (size_t)M * ldc * ((size_t)B * nz + (size_t)S * B * fwd_slots()) + nyq_bytes(B);
         }
-        return celem() * (size_t)M * ldc * (size_t)adj_chunk() * ((size_t)B * n_spec + (size_t)ngrp * B * nz);
+        return celem() * (size_t)M * ldc * (size_t)adj_chunk() * ((size_t)B * fwd_slots() + (size_t)ngrp * B * nz);
     }
 };
 
@@ -718,7 +719,7 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
     // group); the inverse row pass sums a chunk's slabs and adds the chunk
     // to g after the first
     const int Tc = p->adj_chunk();
-    const size_t rstride = (size_t)batch * p->n_spec * p->M * p->ldc;
+    const size_t rstride = (size_t)batch * p->fwd_slots() * p->M * p->ldc;
     const size_t gstride = (size_t)batch * p->nz * p->M * p->ldc;
     const size_t plane = (size_t)p->nx * p->ny;
     char *R = (char *)workspace;
@@ -728,6 +729,46 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
     const double scale = kGrav / ((double)p->py * p->M);
     const gf::NyqSplit none{nullptr, 0, 0};
     mark(p, GF_OP_ADJOINT, 0, st);
+    if (p->levels_blocked()) {
+        // passes of up to levels_per_pass() levels: one row transform of the
+        // pass's residual planes into level-major slots, one column pass
+        // into the pass's layer slab
+        const int per = p->levels_per_pass(), npass = p->adj_passes();
+        for (int q0 = 0; q0 < npass; q0 += Tc) {
+            const int qc = std::min(Tc, npass - q0);
+            for (int jq = 0; jq < qc; ++jq) {
+                const int t0 = (q0 + jq) * per;
+                const int nlev = std::min(per, p->nt - t0);
+                gf::RowCombo cmb{};
+                for (int j = 0; j < nlev; ++j)
+                    for (int sl = 0; sl < p->n_spec; ++sl) {
+                        const int k = j * p->n_spec + sl;
+                        cmb.nterm[k] = p->in_combo.nterm[sl];
+                        for (int i = 0; i < p->in_combo.nterm[sl]; ++i) {
+                            cmb.src[k][i] = j * p->n_out + p->in_combo.src[sl][i];
+                            cmb.w[k][i] = p->in_combo.w[sl][i];
+                        }
+                    }
+                char *Rq = R + p->celem() * (size_t)jq * rstride;
+                if (gf::launch_row_r2c(p->fp64(), p->px, (const char *)r + p->elem() * (size_t)t0 * p->n_out * plane,
+                                       p->nx, p->nx, p->ny, p->ldc, nlev * p->n_spec, p->nt * p->n_out, batch, cmb,
+                                       Rq, p->tw, p->twlog, st) != 0)
+                    return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
+                if (q0 + jq == 0) mark(p, GF_OP_ADJOINT, 1, st);
+                if (gf::launch_col_adjoint_levels(p->fp64(), p->py, Rq, p->spec_window(0, t0),
+                                                  Gt + p->celem() * (size_t)jq * gstride, batch, p->nz, p->M, p->ny,
+                                                  p->ldc, p->n_spec, nlev, S, lps, nq, p->imag_mask, p->yodd_mask,
+                                                  p->tw, p->twlog, st) != 0)
+                    return fail(GF_EDEVICE, "column pass launch: %s", hipGetErrorString(hipGetLastError()));
+            }
+            if (q0 + qc == npass) mark(p, GF_OP_ADJOINT, 2, st);
+            if (gf::launch_row_c2r(p->fp64(), p->px, Gt, (long)gstride, qc, p->nz, p->ny, p->ldc, p->nz, batch, ident,
+                                   none, g, p->nx, scale, p->tw, p->twlog, st, 0, q0 > 0) != 0)
+                return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+        }
+        mark(p, GF_OP_ADJOINT, 3, st);
+        return GF_OK;
+    }
     for (int t0 = 0; t0 < p->nt; t0 += Tc) {
         const int tc = std::min(Tc, p->nt - t0);
         for (int j = 0; j < tc; ++j) {

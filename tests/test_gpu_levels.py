@@ -141,8 +141,9 @@ def test_levels_medium_sampled(gf, orc, mask):
 @pytest.mark.parametrize("mask", [0x1, 0x181, 0x41])
 def test_levels_blocked_passes(gf, orc, mask, prec):
     """Every level of every station against single-plane plans at the
-    level's height (the same operator through the one-level kernels), a
-    sample against the oracle, and batch = single bitwise."""
+    level's height (the same operator through the one-level kernels), the
+    adjoint against the sum of theirs and by the dot product, a sample
+    against the oracle, and batch = single bitwise."""
     g = Geometry(40, 130, 7, 20.0, 25.0, 15.0, 7.0)
     levels = 9
     dt = torch.float64 if prec == "f64" else torch.float32
@@ -155,12 +156,23 @@ def test_levels_blocked_passes(gf, orc, mask, prec):
         one = p.forward(x[b]).double().cpu().numpy()
         assert np.array_equal(d[b], one), b
     close = 1e-12 if prec == "f64" else 1e-6
+    rng = np.random.default_rng(58)
+    r = torch.from_numpy(rng.standard_normal(d.shape)).to("cuda", dt)
+    g_out = p.adjoint(r).double().cpu().numpy()
+    for b in range(2):
+        assert np.array_equal(g_out[b], p.adjoint(r[b]).double().cpu().numpy()), b
+    g_want = np.zeros_like(g_out)
     for t in range(levels):
         q = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz, mask, prec)
         want = q.forward(x).double().cpu().numpy()
+        g_want += q.adjoint(r[:, t].contiguous()).double().cpu().numpy()
         q.close()
         for c in range(want.shape[1]):
             assert rel(d[:, t, c], want[:, c]) <= close, (t, c)
+    assert rel(g_out, g_want) <= close
+    rn = r.double().cpu().numpy()
+    lhs, rhs = float(np.sum(d * rn)), float(np.sum(rho * g_out))
+    assert abs(lhs - rhs) <= DOT[prec] * np.linalg.norm(d) * np.linalg.norm(rn), (lhs, rhs)
     comps = [c for c in range(9) if mask >> c & 1]
     st = np.array([(0, 0), (g.nx - 1, g.ny - 1), (g.nx // 2, g.ny // 2), (g.nx // 3, (2 * g.ny) // 3)])
     want = orc.forward_levels(g, rho[1], levels, st)          # (levels, nst, NCOMP)
