@@ -48,10 +48,16 @@ class GeometryKey:
     h: float
     components: int
     zedges: Optional[Tuple[float, ...]] = None   # layered mesh: nz + 1 layer-edge depths (dz unused)
+    levels: int = 1                               # observation planes dz apart (equal-dimension survey)
 
     @property
     def n_out(self):
         return bin(self.components & 0x1FF).count("1")
+
+    @property
+    def data_shape(self):
+        """One model's data: [levels][C][ny][nx] (levels dropped for one plane)."""
+        return ((self.levels,) if self.levels > 1 else ()) + (self.n_out, self.ny, self.nx)
 
     @property
     def n_spec(self):
@@ -96,13 +102,14 @@ def _circulant(n):
 def spectra_bytes(key: GeometryKey, elem: int) -> int:
     """Resident spectra of a plan: one real per frequency of the quarter plane
     for each stored component and layer."""
-    return key.n_spec * key.nz * (_circulant(key.nx) // 2 + 1) * (_circulant(key.ny) // 2 + 1) * elem
+    layers = key.nz + key.levels - 1
+    return key.n_spec * layers * (_circulant(key.nx) // 2 + 1) * (_circulant(key.ny) // 2 + 1) * elem
 
 
 def io_bytes(key: GeometryKey, op: str, batch: int, elem: int) -> int:
     plane = key.nx * key.ny
     model = key.nz * plane
-    data = key.n_out * plane
+    data = key.levels * key.n_out * plane
     return batch * (model + data) * elem
 
 
@@ -293,7 +300,11 @@ class GpuExecutor:
     def plan_for(self, key):
         p = self.plans.get(key)
         if p is None:
-            if key.zedges is None:
+            if key.levels > 1:
+                p = self.op_mod.plan_levels(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.levels,
+                                            key.components, self.precision, device=self.device,
+                                            stream=self.plan_stream)
+            elif key.zedges is None:
                 p = self.op_mod.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components,
                                      self.precision, device=self.device, stream=self.plan_stream)
             else:
@@ -311,13 +322,17 @@ class GpuExecutor:
         # forward: row-transformed model, up to 32 layer splits of partial
         # data and up to 32 Nyquist chunks; adjoint: the residual's spectra
         # and one model-sized slab per group of six spectra
+        # with several levels a column pass may carry up to six output slots
+        # and the adjoint keeps up to four passes' slabs
         ux = _circulant(key.nx) // 2 + 1
         nspec = key.n_spec
         groups = (nspec + 5) // 6
+        slots = max(nspec, 6) if key.levels > 1 else nspec
+        chunk = min(key.levels, 4)
         splits = 32
         per = 2 * self.elem * ux * (key.ny + 1)
-        fwd = per * batch * (key.nz + splits * nspec) + self.elem * splits * batch * nspec * (key.ny + 1)
-        adj = per * batch * (nspec + groups * key.nz)
+        fwd = per * batch * (key.nz + splits * slots) + self.elem * splits * batch * slots * (key.ny + 1)
+        adj = per * batch * chunk * (slots + groups * key.nz)
         return max(fwd, adj)
 
     def is_resident(self, key):
@@ -337,9 +352,9 @@ class GpuExecutor:
         B = sum(r.batch for r in reqs)
         if op == "forward":
             shape_in = (B, key.nz, key.ny, key.nx)
-            shape_out = (B, key.n_out, key.ny, key.nx)
+            shape_out = (B,) + key.data_shape
         else:
-            shape_in = (B, key.n_out, key.ny, key.nx)
+            shape_in = (B,) + key.data_shape
             shape_out = (B, key.nz, key.ny, key.nx)
         with torch.cuda.stream(st):
             x = torch.empty(shape_in, dtype=self.dtype, device=self.device)

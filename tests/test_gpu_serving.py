@@ -42,12 +42,15 @@ def test_served_equals_alone(gf, orc):
         op = "forward" if rng.random() < 0.5 else "adjoint"
         B = int(rng.integers(1, 5))
         # some geometries are layered meshes (thickening layers, buried top)
-        zedges = None
-        if rng.random() < 0.3:
+        # some geometries are layered meshes, some have three observation levels
+        zedges, levels = None, 1
+        u = rng.random()
+        if u < 0.25:
             zedges = tuple(float(v) for v in 5.0 + np.concatenate([[0.0], np.cumsum(6.0 * 1.2 ** np.arange(nz))]))
-        key = GeometryKey(n, n, nz, 20.0, 20.0, 20.0, 10.0, comps, zedges)
-        C = key.n_out
-        shape = (B, nz, n, n) if op == "forward" else (B, C, n, n)
+        elif u < 0.5:
+            levels = 3
+        key = GeometryKey(n, n, nz, 20.0, 20.0, 20.0, 10.0, comps, zedges, levels)
+        shape = (B, nz, n, n) if op == "forward" else (B,) + key.data_shape
         x = torch.from_numpy(rng.uniform(-500, 500, size=shape).astype(np.float32)).pin_memory()
         specs.append((key, op, x))
     ex = GpuExecutor("f32", 4)
@@ -67,7 +70,10 @@ def test_served_equals_alone(gf, orc):
     plans = {}
     for (key, op, x), r in zip(specs, reqs):
         if key not in plans:
-            if key.zedges is None:
+            if key.levels > 1:
+                plans[key] = gf.plan_levels(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.levels,
+                                            key.components, "f32")
+            elif key.zedges is None:
                 plans[key] = gf.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components, "f32")
             else:
                 plans[key] = gf.plan_layered(key.nx, key.ny, key.dx, key.dy, key.zedges, key.h, key.components,
@@ -87,18 +93,23 @@ def test_served_equals_alone(gf, orc):
     from synth import Geometry
     seen = set()
     for (key, op, x), r in zip(specs, reqs):
-        kind = key.zedges is not None
+        kind = (key.zedges is not None, key.levels)
         if op == "forward" and kind not in seen:
             seen.add(kind)
             g = Geometry(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h)
             st = np.array([(0, 0), (key.nx // 2, key.ny // 3), (key.nx - 1, key.ny - 1)])
-            want = orc.forward(g, x[0].double().numpy(), st, zedges=key.zedges)
-            got = r.result[0].double().numpy()
+            if key.levels > 1:
+                want_l = orc.forward_levels(g, x[0].double().numpy(), key.levels, st)
+                got_l = r.result[0].double().numpy()
+            else:
+                want_l = orc.forward(g, x[0].double().numpy(), st, zedges=key.zedges)[None]
+                got_l = r.result[0].double().numpy()[None]
             comps = [c for c in range(9) if key.components >> c & 1]
-            for i, c in enumerate(comps):
-                gv = got[i][st[:, 1], st[:, 0]]
-                e = np.linalg.norm(gv - want[:, c]) / np.linalg.norm(want[:, c])
-                assert e <= 1e-5, (key, c, e)
+            for t in range(want_l.shape[0]):
+                for i, c in enumerate(comps):
+                    gv = got_l[t][i][st[:, 1], st[:, 0]]
+                    e = np.linalg.norm(gv - want_l[t][:, c]) / np.linalg.norm(want_l[t][:, c])
+                    assert e <= 1e-5, (key, t, c, e)
     assert seen, "no served forward to check"
 
 
@@ -108,12 +119,16 @@ def test_workspace_estimate_bounds_the_plan(gf, prec):
     estimate must not fall below what the plan then asks for."""
     from paper_2005_10160_amd.serve import GeometryKey, GpuExecutor
     ex = GpuExecutor(prec, 1)
-    cases = [(64, 8, 0x1), (64, 8, 0x1FF), (100, 37, 0x1FF), (128, 16, 0x3F), (33, 5, 0x181), (96, 3, 0x7F)]
+    cases = [(64, 8, 0x1), (64, 8, 0x1FF), (100, 37, 0x1FF), (128, 16, 0x3F), (33, 5, 0x181), (96, 3, 0x7F),
+             (140, 9, 0x1), (140, 9, 0x41)]
     for n, nz, comps in cases:
-        for zedges in (None, tuple(float(v) for v in np.cumsum(np.r_[0.0, 3.0 * 1.3 ** np.arange(nz)]))):
-            key = GeometryKey(n, n + 7, nz, 20.0, 20.0, 20.0, 10.0, comps, zedges)
+        for zedges, levels in ((None, 1), (tuple(float(v) for v in np.cumsum(np.r_[0.0, 3.0 * 1.3 ** np.arange(nz)])), 1),
+                               (None, 3), (None, 11)):
+            key = GeometryKey(n, n + 7, nz, 20.0, 20.0, 20.0, 10.0, comps, zedges, levels)
             est = {(op, B): ex.workspace_bytes(key, op, B) for op in ("forward", "adjoint") for B in (1, 3, 16)}
-            if zedges is None:
+            if levels > 1:
+                p = gf.plan_levels(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, levels, comps, prec)
+            elif zedges is None:
                 p = gf.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, comps, prec)
             else:
                 p = gf.plan_layered(key.nx, key.ny, key.dx, key.dy, zedges, key.h, comps, prec)
