@@ -1,0 +1,89 @@
+"""The C ABI on the GPU: the plan's internal workspace (workspace NULL, up
+to max_batch models) gives the same results as a caller's workspace, and
+too small a workspace or too large a batch is refused with GF_EBUSY before
+anything is enqueued.  Uniform nine-component, observation-level and
+layered plans."""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+from synth import Geometry, tiny_density
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2005_10160_amd as gf
+    from paper_2005_10160_amd import _native
+    _native.load()
+    return gf
+
+
+def vp(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+@pytest.mark.parametrize("kind", ["uniform", "levels", "layered"])
+def test_internal_workspace_and_busy(gf, kind):
+    from paper_2005_10160_amd import _native
+    lib = _native.load()
+    g = Geometry(40, 130, 6, 20.0, 25.0, 15.0, 7.0)
+    zed = (ctypes.c_double * 7)(*[0.0, 4.0, 9.0, 15.0, 23.0, 33.0, 46.0])
+    h = ctypes.c_void_p()
+    st = torch.cuda.current_stream()
+    sh = ctypes.c_void_p(st.cuda_stream)
+    if kind == "uniform":
+        mask, rc = 0x1FF, lib.gf_plan_create(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ctypes.c_uint(0x1FF), 0, 2,
+                                             sh, ctypes.byref(h))
+        p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, "f64")
+    elif kind == "levels":
+        mask, rc = 0x1, lib.gf_plan_create_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 7, ctypes.c_uint(0x1), 0,
+                                                  2, sh, ctypes.byref(h))
+        p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 7, mask, "f64")
+    else:
+        mask, rc = 0x3F, lib.gf_plan_create_layered(g.nx, g.ny, g.nz, g.dx, g.dy, zed, g.h, ctypes.c_uint(0x3F), 0,
+                                                    2, sh, ctypes.byref(h))
+        p = gf.plan_layered(g.nx, g.ny, g.dx, g.dy, list(zed), g.h, mask, "f64")
+    assert rc == _native.GF_OK, lib.gf_last_error()
+    try:
+        info = _native.PlanInfo()
+        assert lib.gf_plan_get_info(h, ctypes.byref(info)) == _native.GF_OK
+        assert info.max_batch == 2 and info.internal_workspace_bytes > 0
+        rho = torch.from_numpy(np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (71, 72, 73)]))
+        rho = rho.cuda()
+        want = p.forward(rho)                                  # the binding's own workspace
+        r = torch.randn(want.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(74)).cuda()
+        want_g = p.adjoint(r)
+        for B in (1, 2):
+            d = torch.empty((B,) + tuple(want.shape[1:]), dtype=torch.float64, device="cuda")
+            assert lib.gf_forward(h, vp(rho), vp(d), B, None, 0, sh) == _native.GF_OK
+            gg = torch.empty((B,) + tuple(rho.shape[1:]), dtype=torch.float64, device="cuda")
+            assert lib.gf_adjoint(h, vp(r), vp(gg), B, None, 0, sh) == _native.GF_OK
+            torch.cuda.synchronize()
+            assert torch.equal(d, want[:B]) and torch.equal(gg, want_g[:B]), B
+        # batch beyond the internal workspace, and a caller's workspace one byte short
+        d = torch.empty_like(want)
+        assert lib.gf_forward(h, vp(rho), vp(d), 3, None, 0, sh) == _native.GF_EBUSY
+        for op, fn, x, y in ((0, lib.gf_forward, rho, d), (1, lib.gf_adjoint, r, torch.empty_like(rho))):
+            need = ctypes.c_size_t()
+            assert lib.gf_workspace_bytes(h, op, 3, ctypes.byref(need)) == _native.GF_OK
+            ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+            assert fn(h, vp(x), vp(y), 3, vp(ws), need.value - 1, sh) == _native.GF_EBUSY
+            assert fn(h, vp(x), vp(y), 3, vp(ws), need.value, sh) == _native.GF_OK
+        torch.cuda.synchronize()
+        assert torch.equal(d, want)
+        # per-pass timing of the last calls
+        assert lib.gf_plan_set_timing(h, 1) == _native.GF_OK
+        assert lib.gf_forward(h, vp(rho), vp(d), 2, None, 0, sh) == _native.GF_OK
+        ms = (ctypes.c_double * 3)()
+        assert lib.gf_plan_last_pass_ms(h, 0, ms) == _native.GF_OK
+        assert all(v >= 0 for v in ms) and sum(ms) > 0
+    finally:
+        lib.gf_plan_destroy(h)
+        p.close()
