@@ -195,6 +195,78 @@ def batched_step(steps, warmup):
     return out
 
 
+def config_table(dev, rho_c3, steps=20, warmup=3):
+    """The per-configuration table: for the tiny (16^2x8, full oracle), the
+    medium (256^2x64, oracle at sampled stations) and the paper-scale grid
+    (oracle at three sampled stations), in FP64 and FP32: median forward and
+    adjoint apply times, effective evaluations per second, compulsory bytes
+    over the forward time as a fraction of 8 TB/s, and the largest relative
+    L2 error over the six components against the long-double oracle."""
+    import torch
+    import oracle
+    import paper_2005_10160_amd as gf
+    from synth import PRESETS, tiny_density, prisms_and_grf, sample_stations
+
+    def median_ms(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(steps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        return statistics.median(ts)
+
+    out = {}
+    cases = [("C1_tiny", PRESETS["tiny"], None), ("C2_medium", PRESETS["medium"], 16),
+             ("C3_paper_scale", PRESETS["paper_scale"], 3)]
+    for name, g, nst in cases:
+        log("bench: config table %s" % name)
+        if name == "C1_tiny":
+            rho = tiny_density(g.nx, g.ny, g.nz)
+        elif name == "C2_medium":
+            rho = prisms_and_grf(g.nx, g.ny, g.nz, 6, 202, 203)
+        else:
+            rho = rho_c3
+        if nst is None:
+            st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
+        elif nst == 3:
+            st = sample_stations(g.nx, g.ny, 0, seed=1)[[8, 0, 3]]
+        else:
+            st = sample_stations(g.nx, g.ny, nst - 9, seed=204)
+        want = oracle.forward(g, rho, st)                     # (nst, NCOMP)
+        row = {"grid": "%dx%dx%d" % (g.nx, g.ny, g.nz), "oracle_stations": int(len(st))}
+        for prec in ("f64", "f32"):
+            dt = torch.float64 if prec == "f64" else torch.float32
+            p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, gf.ALL6, prec, device=dev)
+            x = torch.from_numpy(rho).to(dev, dt).unsqueeze(0)
+            d = torch.empty((1,) + p.data_shape, dtype=dt, device=dev)
+            gt = torch.empty_like(x)
+            ws = torch.empty(max(p.workspace_bytes("forward", 1), p.workspace_bytes("adjoint", 1)),
+                             dtype=torch.uint8, device=dev)
+            tf = median_ms(lambda: p.forward(x, d, ws))
+            ta = median_ms(lambda: p.adjoint(d, gt, ws))
+            dn = d[0].double().cpu().numpy()
+            err = 0.0
+            for c in range(6):
+                gv = dn[c][st[:, 1], st[:, 0]]
+                err = max(err, float(np.linalg.norm(gv - want[:, c]) / np.linalg.norm(want[:, c])))
+            s_el = 8 if prec == "f64" else 4
+            comp = p.spectra_bytes + s_el * (g.nz * g.nx * g.ny + 6 * g.nx * g.ny)
+            row[prec] = {"forward_ms": round(tf, 4), "adjoint_ms": round(ta, 4),
+                         "effective_evals_per_s": 6.0 * g.nd * g.nm / (tf * 1e-3),
+                         "compulsory_frac_of_8TBs": round(comp / (tf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                         "max_rel_l2_vs_oracle": err}
+            p.close()
+            del x, d, gt, ws
+        out[name] = row
+    return out
+
+
 def stream_bandwidth(dev, gib=2, reps=10):
     """Practical streaming rates of the device, timed with HIP events: a
     plain device-to-device copy of `gib` GiB (GB/s of bytes read plus
@@ -269,6 +341,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-model inversion-step timing")
     ap.add_argument("--no-sets", action="store_true", help="skip the gz/gx/gy and nine-component timings")
+    ap.add_argument("--configs", action="store_true",
+                    help="add the per-configuration table (tiny, medium, paper scale: times and oracle errors)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="length of the replayed request trace (0: no serving run)")
     ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
@@ -461,6 +535,9 @@ def main():
 
     if not args.no_batched and not args.small:
         line["batched"] = batched_step(5, 1)
+
+    if args.configs:
+        line["configs"] = config_table(dev, rho_np)
 
     if args.serve_seconds > 0:
         from paper_2005_10160_amd import serve
