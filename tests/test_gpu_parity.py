@@ -382,3 +382,33 @@ def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
     e = rel(ga, wa)
     note("sweep %dx%d %s: adjoint rel %.2e" % (nx, ny, prec, e))
     assert e <= tol
+
+
+@pytest.mark.parametrize("prec,mask", [("f32", 0x3F), ("f64", 0x1), ("f64", 0x3F)])
+def test_largest_grid(gf, orc, prec, mask):
+    """nx = ny = 2048, the largest grid (circulant 4096 x 4096, row and
+    column transforms of the longest lengths together), three layers: FP32
+    with six components and FP64 with gz alone against the direct sum at
+    sampled stations; FP64 with six spectra does not fit the column pass's
+    LDS and is refused with GF_EUNSUPPORTED."""
+    from paper_2005_10160_amd import _native
+    g = Geometry(2048, 2048, 3, 10.0, 10.0, 10.0, 5.0)
+    if prec == "f64" and mask != 0x1:
+        with pytest.raises(_native.GravFFTError) as ei:
+            gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, prec)
+        assert ei.value.status == _native.GF_EUNSUPPORTED
+        return
+    rng = np.random.default_rng(2048)
+    rho = rng.uniform(-500.0, 500.0, size=(g.nz, g.ny, g.nx))
+    note("largest grid %s %s: forward" % (prec, hex(mask)))
+    got = run_forward(gf, g, rho, mask=mask, prec=prec)
+    st = sample_stations(g.nx, g.ny, 2, seed=2049)
+    note("largest grid: oracle at %d stations" % len(st))
+    want = orc.forward(g, rho, st)
+    comps = [c for c in range(9) if mask >> c & 1]
+    tol = TOL64 if prec == "f64" else TOL32
+    for i, c in enumerate(comps):
+        gv = got[i][st[:, 1], st[:, 0]]
+        e = rel(gv, want[:, c])
+        note("largest grid %s %s sampled rel %.2e" % (prec, NAMES[c], e))
+        assert e <= tol, (NAMES[c], e)
