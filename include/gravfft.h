@@ -116,8 +116,8 @@ typedef struct {
  * purely real or purely imaginary and even or odd in each frequency axis
  * (the potential-field symmetry of section 2.2).  Every output component
  * except gzz has its own spectrum; gzz reuses those of gxx and gyy.  Plans
- * with more than six spectra (gx or gy with the full tensor) run the column
- * pass once per group of up to six.
+ * with more spectra than one column-pass launch holds (six; three or one at
+ * the longest FP64 transform lengths) run the column pass once per group.
  *
  *   nx, ny, nz  >= 1, nx, ny <= 2048           grid size
  *   dx, dy, dz  > 0                            cell size, metres

@@ -1501,11 +1501,20 @@ int launch_col_adjoint_levels(bool fp64, int py, const void *R, const void *spec
 #undef CASE
 }
 
-bool col_levels_blocked(int py)
+template <typename T, int N>
+static bool levels_supported_of()
+{
+    if constexpr (use_ws<N>())
+        return WsCfg<T, N>::lds_bytes(6) <= lds_limit();
+    else
+        return false;
+}
+
+bool col_levels_supported(bool fp64, int py)
 {
 #define CASE(NN) \
     case NN:     \
-        return use_ws<NN>();
+        return fp64 ? levels_supported_of<double, NN>() : levels_supported_of<float, NN>();
     switch (py) {
         GF_COL_SIZES(CASE)
     default:

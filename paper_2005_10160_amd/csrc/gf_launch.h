@@ -8,7 +8,8 @@ namespace gf {
 
 // Most output components of one plan (gz, the six tensor components, gx, gy)
 // and most spectra one column-pass launch carries; plans with more resident
-// spectra run the column pass once per group of at most kColMaxSpec.
+// spectra run the column pass once per group of at most kColMaxSpec (or of
+// three or one where the transform length leaves less LDS).
 constexpr int kMaxOut = 9;
 constexpr int kColMaxSpec = 6;
 
@@ -96,8 +97,8 @@ int launch_col_adjoint(bool fp64, int py, const void *R, const void *spec, void 
 // Forward column pass of nlev observation levels at once for Cs <= 3
 // spectra (nlev * Cs <= 6): level j sums spectral layers n + j from `spec`
 // over model layers n; D and nq.Dny hold nlev * Cs slots (level-major).
-// Only for transform lengths that run in the wave split
-// (col_levels_blocked).
+// Only where the transform length runs in the wave split and its buffers fit
+// in LDS (col_levels_supported).
 int launch_col_forward_levels(bool fp64, int py, const void *R, const void *spec, void *D, int B, int nz, int M,
                               int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
                               unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
@@ -106,7 +107,7 @@ int launch_col_forward_levels(bool fp64, int py, const void *R, const void *spec
 int launch_col_adjoint_levels(bool fp64, int py, const void *R, const void *spec, void *Gout, int B, int nz, int M,
                               int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
                               unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
-bool col_levels_blocked(int py);
+bool col_levels_supported(bool fp64, int py);
 
 // Plan time: column FFT of the row-transformed kernel fields and extraction
 // of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).

@@ -121,11 +121,12 @@ struct gf_plan {
     int spec_codes[8];
     unsigned spec_mask;
     unsigned imag_mask, yodd_mask;  // over spectral slots
-    // Spectral slots in groups of at most kColMaxSpec, one column-pass
-    // launch each; group g holds slots [grp_c0[g], grp_c0[g] + grp_cs[g]) and
-    // its spectra are stored apart as [nzs][M+1][grp_cs[g]][QP].
-    int ngrp;
-    int grp_c0[2], grp_cs[2];
+    // Spectral slots in groups of at most gmax (six, or three or one where
+    // the transform length leaves less LDS), one column-pass launch each;
+    // group g holds slots [grp_c0[g], grp_c0[g] + grp_cs[g]) and its spectra
+    // are stored apart as [nzs][M+1][grp_cs[g]][QP].
+    int ngrp, gmax;
+    int grp_c0[8], grp_cs[8];
     gf::RowCombo out_combo;         // output o from spectral slots
     gf::RowCombo in_combo;          // adjoint: spectral slot s from input components
     void *spec = nullptr;
@@ -154,7 +155,7 @@ struct gf_plan {
     // Forward of several levels per column pass (one density transform per
     // layer for all of them, spectral layers in an LDS ring): plans of up to
     // three spectra at wave-split transform lengths
-    bool levels_blocked() const { return nt > 1 && n_spec <= 3 && gf::col_levels_blocked(py); }
+    bool levels_blocked() const { return nt > 1 && n_spec <= 3 && gf::col_levels_supported(fp64(), py); }
     int levels_per_pass() const { return levels_blocked() ? std::min(nt, 6 / n_spec) : 1; }
     // slots of the forward column pass's outputs (D and Dny)
     int fwd_slots() const { return levels_per_pass() * n_spec; }
@@ -423,10 +424,20 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
             if (is_imag(c)) p->imag_mask |= 1u << s;
             if (is_yodd(c)) p->yodd_mask |= 1u << s;
         }
-    p->ngrp = (p->n_spec + gf::kColMaxSpec - 1) / gf::kColMaxSpec;
+    p->gmax = 0;
+    for (int c : {gf::kColMaxSpec, 3, 1})
+        if (gf::col_supported(precision == GF_F64, p->py, c)) {
+            p->gmax = c;
+            break;
+        }
+    if (p->gmax == 0) {
+        free_plan(p);
+        return fail(GF_EUNSUPPORTED, "transform length %d does not fit in LDS", p->py);
+    }
+    p->ngrp = (p->n_spec + p->gmax - 1) / p->gmax;
     for (int g = 0; g < p->ngrp; ++g) {
-        p->grp_c0[g] = g * gf::kColMaxSpec;
-        p->grp_cs[g] = std::min(gf::kColMaxSpec, p->n_spec - p->grp_c0[g]);
+        p->grp_c0[g] = g * p->gmax;
+        p->grp_cs[g] = std::min(p->gmax, p->n_spec - p->grp_c0[g]);
     }
     std::memset(&p->out_combo, 0, sizeof(p->out_combo));
     for (int o = 0; o < p->n_out; ++o) {
@@ -867,7 +878,7 @@ gf_status gf_debug_spectrum(const gf_plan *p, unsigned component, int n, double 
         if (c != 6 && component == (1u << c)) code = c;
     const int slot_all = code >= 0 ? p->slot_of(code) : -1;
     if (slot_all < 0) return fail(GF_EINVAL, "component 0x%x has no resident spectrum", component);
-    const int gr = slot_all / gf::kColMaxSpec, slot = slot_all - p->grp_c0[gr], cs = p->grp_cs[gr];
+    const int gr = slot_all / p->gmax, slot = slot_all - p->grp_c0[gr], cs = p->grp_cs[gr];
     // group layout [n][row][slot][QP], rows in the order kx = 0, Px/2, 1, ..., Px/2-1
     const size_t layer = (size_t)p->U * cs * p->QP;
     std::vector<double> lay(layer);

@@ -181,3 +181,26 @@ def test_levels_blocked_passes(gf, orc, mask, prec):
             e = rel(d[1, t, i][st[:, 1], st[:, 0]], want[t, :, c])
             assert e <= TOL[prec], (t, NAMES[c], e)
     p.close()
+
+
+def test_levels_longest_columns_fp64(gf, orc):
+    """Column length 4096 in FP64 leaves LDS for one spectrum per launch:
+    levels run one per pass there (the several-level passes need six
+    spectrum rows), forward and adjoint, against the oracle and the dot
+    product."""
+    g = Geometry(6, 2048, 2, 30.0, 10.0, 10.0, 5.0)
+    levels = 3
+    rho = tiny_density(g.nx, g.ny, g.nz, seed=59, block=None)
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, 0x181, "f64")
+    d = p.forward(torch.from_numpy(rho).cuda()).cpu().numpy()
+    st = np.array([(0, 0), (5, 2047), (3, 1024), (2, 700)])
+    want = orc.forward_levels(g, rho, levels, st)
+    for t in range(levels):
+        for i, c in enumerate((0, 7, 8)):
+            e = rel(d[t, i][st[:, 1], st[:, 0]], want[t, :, c])
+            assert e <= TOL["f64"], (t, NAMES[c], e)
+    r = np.random.default_rng(60).standard_normal(d.shape)
+    gt = p.adjoint(torch.from_numpy(r).cuda()).cpu().numpy()
+    lhs, rhs = float(np.sum(d * r)), float(np.sum(rho * gt))
+    assert abs(lhs - rhs) <= DOT["f64"] * np.linalg.norm(d) * np.linalg.norm(r)
+    p.close()

@@ -345,19 +345,11 @@ def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
     """Forward and adjoint at every row and column transform length against
     the direct sum at sampled stations (corners, centre, an off-centre
     station; nz = 3, all nine components).  The FP64 column pass of length
-    4096 does not fit in LDS: its plan must fail with GF_EUNSUPPORTED."""
-    from paper_2005_10160_amd import _native
+    4096 holds one spectrum per launch in LDS: there the eight spectra run
+    as eight column-pass groups."""
     g = Geometry(nx, ny, 3, 20.0, 25.0, 15.0, 7.0)
     rng = np.random.default_rng(nx * 7919 + ny)
     rho = rng.uniform(-500.0, 500.0, size=(g.nz, ny, nx))
-    py = 16
-    while py < 2 * ny - 1:
-        py *= 2
-    if prec == "f64" and py > 2048:
-        with pytest.raises(_native.GravFFTError) as ei:
-            gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, prec)
-        assert ei.value.status == _native.GF_EUNSUPPORTED
-        return
     note("sweep %dx%d %s: forward" % (nx, ny, prec))
     got = run_forward(gf, g, rho, mask=ALL9, prec=prec)
     st = np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 2), (nx // 3, (2 * ny) // 3), (nx - 1, 0)])
@@ -388,16 +380,10 @@ def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
 def test_largest_grid(gf, orc, prec, mask):
     """nx = ny = 2048, the largest grid (circulant 4096 x 4096, row and
     column transforms of the longest lengths together), three layers: FP32
-    with six components and FP64 with gz alone against the direct sum at
-    sampled stations; FP64 with six spectra does not fit the column pass's
-    LDS and is refused with GF_EUNSUPPORTED."""
-    from paper_2005_10160_amd import _native
+    with six components, FP64 with gz alone and FP64 with six components
+    (one spectrum per column-pass launch at this length) against the direct
+    sum at sampled stations."""
     g = Geometry(2048, 2048, 3, 10.0, 10.0, 10.0, 5.0)
-    if prec == "f64" and mask != 0x1:
-        with pytest.raises(_native.GravFFTError) as ei:
-            gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, mask, prec)
-        assert ei.value.status == _native.GF_EUNSUPPORTED
-        return
     rng = np.random.default_rng(2048)
     rho = rng.uniform(-500.0, 500.0, size=(g.nz, g.ny, g.nx))
     note("largest grid %s %s: forward" % (prec, hex(mask)))
