@@ -204,3 +204,24 @@ def test_levels_longest_columns_fp64(gf, orc):
     lhs, rhs = float(np.sum(d * r)), float(np.sum(rho * gt))
     assert abs(lhs - rhs) <= DOT["f64"] * np.linalg.norm(d) * np.linalg.norm(r)
     p.close()
+
+
+@pytest.mark.parametrize("kind", ["levels", "layered"])
+def test_autograd_through_level_and_layered_plans(gf, kind):
+    """GravityOperator on a level plan and on a layered plan: the gradient of
+    1/2 |G m - d|^2 that autograd returns is G^T (G m - d) from the adjoint."""
+    g = Geometry(20, 140, 5, 20.0, 25.0, 15.0, 7.0)
+    if kind == "levels":
+        p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 4, 0x41, "f64")
+    else:
+        p = gf.plan_layered(g.nx, g.ny, g.dx, g.dy, [0.0, 3.0, 8.0, 15.0, 30.0, 50.0], g.h, 0x181, "f64")
+    op = gf.GravityOperator(p)
+    m = torch.from_numpy(tiny_density(g.nx, g.ny, g.nz, seed=62, block=None)).cuda().requires_grad_(True)
+    d_obs = torch.randn((1,) + p.data_shape, dtype=torch.float64,
+                        generator=torch.Generator().manual_seed(63)).cuda()[0] * 1e-6
+    loss = 0.5 * ((op(m) - d_obs) ** 2).sum()
+    loss.backward()
+    with torch.no_grad():
+        want = p.adjoint((p.forward(m) - d_obs).contiguous())
+    assert torch.equal(m.grad, want)
+    p.close()
