@@ -214,3 +214,20 @@ def test_failed_launch_rejects_its_group_only():
     assert bad.status == "rejected" and "boom" in bad.error
     assert good.status == "done"
     assert s.in_use == 0
+
+
+def test_level_and_layered_keys():
+    """Keys of observation-level plans carry one data plane per level and
+    spectra for nz + levels - 1 layer offsets; gx and gy each add a
+    spectrum, gzz none beyond gxx and gyy."""
+    k = GeometryKey(32, 48, 10, 20.0, 20.0, 20.0, 10.0, 0x1, None, 4)
+    assert k.data_shape == (4, 1, 48, 32)
+    assert spectra_bytes(k, 4) == 1 * 13 * 33 * 65 * 4     # circulants 64 x 128
+    assert io_bytes(k, "forward", 2, 4) == 2 * (10 * 32 * 48 + 4 * 32 * 48) * 4
+    one = GeometryKey(32, 48, 10, 20.0, 20.0, 20.0, 10.0, 0x1FF)
+    assert one.data_shape == (9, 48, 32) and one.n_spec == 8
+    assert GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x40).n_spec == 2
+    assert GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x180).n_spec == 2
+    lay = GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x1, (0.0, 1.0, 3.0))
+    assert lay != GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x1, (0.0, 1.0, 4.0))
+    assert lay != GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x1)
