@@ -316,6 +316,10 @@ def cpu_baseline(g, rho_np, n_stations, threads):
     dt = time.perf_counter() - t0
     evals = len(st) * g.nm * 6
     full = 6.0 * g.nd * g.nm
+    # the same direct sum built in plain double, timed beside it
+    t0 = time.perf_counter()
+    oracle.forward_fp64(g, rho_np, st)
+    dt64 = time.perf_counter() - t0
     return {
         "value": evals / dt,
         "unit": "kernel-evals/s",
@@ -325,6 +329,8 @@ def cpu_baseline(g, rho_np, n_stations, threads):
                   "all %d cells, 6 components counted; %.1f s wall" % (len(st), g.nm, dt),
         "cpu": cpu_model(),
         "extrapolated_full_apply_s": full / (evals / dt),
+        "fp64_mode": {"value": evals / dt64, "unit": "kernel-evals/s",
+                      "sample": "the same stations, plain double arithmetic; %.1f s wall" % dt64},
     }
 
 

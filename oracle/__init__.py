@@ -25,29 +25,34 @@ NCOMP = 9
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gravity_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_gravity_oracle.so")
+_LIB64_PATH = os.path.join(_HERE, "_gravity_oracle_f64.so")
 _lock = threading.Lock()
 _lib = None
+_lib64 = None
 
 
 def build(force=False):
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
-    if not force and os.path.exists(_LIB_PATH) and os.path.getmtime(_LIB_PATH) >= os.path.getmtime(_SRC):
-        return _LIB_PATH
-    tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           "-Wall", "-o", tmp, _SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, _LIB_PATH)
+    """Compile the oracle with gcc (no fast-math, no FMA contraction): the
+    long-double reference and, from the same source, its plain-double build
+    (timed beside it, never a reference)."""
+    for path, extra in ((_LIB_PATH, []), (_LIB64_PATH, ["-DORC_FP64"])):
+        if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(_SRC):
+            continue
+        tmp = path + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall"] + extra + ["-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, path)
     return _LIB_PATH
 
 
-def _load():
-    global _lib
+def _load(fp64=False):
+    global _lib, _lib64
     with _lock:
-        if _lib is not None:
-            return _lib
+        if (_lib64 if fp64 else _lib) is not None:
+            return _lib64 if fp64 else _lib
         build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        lib = ctypes.CDLL(_LIB64_PATH if fp64 else _LIB_PATH)
         d, i, u = ctypes.c_double, ctypes.c_int, ctypes.c_uint
         pd = ctypes.POINTER(ctypes.c_double)
         pi = ctypes.POINTER(ctypes.c_int)
@@ -78,7 +83,10 @@ def _load():
         lib.orc_max_threads.restype = i
         lib.orc_set_threads.argtypes = [i]
         lib.orc_grav_const.restype = d
-        _lib = lib
+        if fp64:
+            _lib64 = lib
+        else:
+            _lib = lib
         return lib
 
 
@@ -177,7 +185,14 @@ def kernel_table(geom, n, mode=0, zedges=None):
     return k.T.reshape(NCOMP, 2 * geom.ny - 1, 2 * geom.nx - 1)
 
 
-def forward(geom, rho, stations=None, zedges=None):
+def forward_fp64(geom, rho, stations=None):
+    """The direct sum of forward() evaluated in plain double (the same code
+    built with double arithmetic): reported for timing and for the size of
+    its rounding, not used as a reference."""
+    return forward(geom, rho, stations, _fp64=True)
+
+
+def forward(geom, rho, stations=None, zedges=None, _fp64=False):
     """Direct sum d = G rho (eq. 3) at stations (array of (p, q)); all
     stations in row order (q major) when None.  rho: (nz,ny,nx) or
     (nb,nz,ny,nx) in kg/m^3.  zedges: nz + 1 layer-edge depths of a layered
@@ -198,7 +213,9 @@ def forward(geom, rho, stations=None, zedges=None):
     sq = np.ascontiguousarray(st[:, 1])
     out = np.zeros((nb, st.shape[0], NCOMP))
     z = _edges(geom, zedges)
-    if z is not None:
+    if _fp64:
+        rc = _load(True).orc_forward(*_geom(geom), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
+    elif z is not None:
         rc = _load().orc_forward_z(*_geom_z(geom, z), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
     else:
         rc = _load().orc_forward(*_geom(geom), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))

@@ -60,19 +60,25 @@
  * half-integer offsets), and the jump of atan(y z / (x r)) across x = 0 is
  * killed by its factor x.
  */
-#include <math.h>
 #include <stdlib.h>
+#include <tgmath.h>
 #include <string.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
 
+/* Built twice: in long double (the reference), and with ORC_FP64 in plain
+ * double, whose timing is reported beside it (same code, type-generic math). */
+#ifdef ORC_FP64
+typedef double ld;
+#else
 typedef long double ld;
+#endif
 
 enum { C_GZ = 0, C_GXX = 1, C_GXY = 2, C_GXZ = 3, C_GYY = 4, C_GYZ = 5, C_GZZ = 6, C_GX = 7, C_GY = 8,
        NCOMP = 9 };
 
-static const ld GRAV = 6.672e-11L; /* eq. 2 */
+static const ld GRAV = (ld)6.672e-11L; /* eq. 2 */
 
 int orc_ncomp(void) { return NCOMP; }
 double orc_grav_const(void) { return (double)GRAV; }
@@ -102,25 +108,25 @@ void orc_set_threads(int n)
 static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
 {
     ld x2 = x * x, y2 = y * y, z2 = z * z;
-    ld r = sqrtl(x2 + y2 + z2);
-    ld sxz = sqrtl(x2 + z2);
-    ld syz = sqrtl(y2 + z2);
-    ld ash_y = asinhl(y / sxz);        /* = ln(y + r) - ln sqrt(x^2+z^2) */
-    ld ash_x = asinhl(x / syz);        /* = ln(x + r) - ln sqrt(y^2+z^2) */
+    ld r = sqrt(x2 + y2 + z2);
+    ld sxz = sqrt(x2 + z2);
+    ld syz = sqrt(y2 + z2);
+    ld ash_y = asinh(y / sxz);        /* = ln(y + r) - ln sqrt(x^2+z^2) */
+    ld ash_x = asinh(x / syz);        /* = ln(x + r) - ln sqrt(y^2+z^2) */
     /* On a corner at x = y = 0 (a station over a cell edge) the terms
      * y asinh(z/sqrt(x^2+y^2)) and x atan(y z / (x r)) have the limit 0:
      * the factor vanishes while asinh grows like ln(1/|y|) and atan stays
      * bounded. */
-    ld sxy = sqrtl(x2 + y2);
-    ld ash_z = sxy > 0 ? asinhl(z / sxy) : 0;   /* only ever multiplied by x or y */
-    ld at_x = x != 0 ? atanl((y * z) / (x * r)) : 0;
-    ld at_y = y != 0 ? atanl((x * z) / (y * r)) : 0;
-    ld at_z = atanl((x * y) / (z * r));
+    ld sxy = sqrt(x2 + y2);
+    ld ash_z = sxy > 0 ? asinh(z / sxy) : 0;   /* only ever multiplied by x or y */
+    ld at_x = x != 0 ? atan((y * z) / (x * r)) : 0;
+    ld at_y = y != 0 ? atan((x * z) / (y * r)) : 0;
+    ld at_z = atan((x * y) / (z * r));
     f[C_GZ] = -(x * ash_y + y * ash_x - z * at_z);
-    f[C_GXX] = -atan2l(y * z, x * r);
-    f[C_GYY] = -atan2l(x * z, y * r);
+    f[C_GXX] = -atan2(y * z, x * r);
+    f[C_GYY] = -atan2(x * z, y * r);
     f[C_GZZ] = -at_z;
-    f[C_GXY] = logl(z + r);
+    f[C_GXY] = log(z + r);
     f[C_GXZ] = ash_y;
     f[C_GYZ] = ash_x;
     f[C_GX] = -(z * ash_y + y * ash_z - x * at_x);
@@ -128,7 +134,7 @@ static void corner_terms(ld x, ld y, ld z, ld f[NCOMP])
 }
 
 /* mu for corner (i,j,k), each 0 = lower bound, 1 = upper bound. */
-static ld corner_sign(int i, int j, int k) { return ((i + j + k) & 1) ? 1.0L : -1.0L; }
+static ld corner_sign(int i, int j, int k) { return ((i + j + k) & 1) ? (ld)1 : (ld)-1; }
 
 /* Kernel of one prism (per unit density, G included) from its corners. */
 static void prism_ld(ld x1, ld x2, ld y1, ld y2, ld z1, ld z2, ld out[NCOMP])
@@ -163,9 +169,9 @@ void orc_prism(double x1, double x2, double y1, double y2, double z1, double z2,
  * guess cos(pi (i+3/4)/(n+1/2)), using the three-term recurrence. */
 static void gl_rule(int n, ld *x, ld *w)
 {
-    const ld PI = 3.141592653589793238462643383279502884L;
+    const ld PI = (ld)3.141592653589793238462643383279502884L;
     for (int i = 0; i < n; ++i) {
-        ld t = cosl(PI * (i + 0.75L) / (n + 0.5L));
+        ld t = cos(PI * (i + (ld)0.75) / (n + (ld)0.5));
         ld dp = 1;
         for (int it = 0; it < 100; ++it) {
             ld p0 = 1, p1 = t;
@@ -178,7 +184,7 @@ static void gl_rule(int n, ld *x, ld *w)
             dp = n * (t * p1 - p0) / (t * t - 1);
             ld dt = p1 / dp;
             t -= dt;
-            if (fabsl(dt) < 1e-19L) break;
+            if (fabs(dt) < (ld)1e-19L) break;
         }
         {
             ld p0 = 1, p1 = t;
@@ -199,7 +205,7 @@ static void gl_rule(int n, ld *x, ld *w)
 static void point_kernel(ld x, ld y, ld z, ld k[NCOMP])
 {
     ld r2 = x * x + y * y + z * z;
-    ld r = sqrtl(r2);
+    ld r = sqrt(r2);
     ld ir3 = 1 / (r2 * r);
     ld ir5 = ir3 / r2;
     k[C_GZ] = GRAV * z * ir3;
@@ -237,8 +243,8 @@ static void gl_adaptive(ld x1, ld x2, ld y1, ld y2, ld z1, ld z2, ld ratio, int 
                         const ld *gw, int depth, ld acc[NCOMP])
 {
     ld cx = (x1 + x2) / 2, cy = (y1 + y2) / 2, cz = (z1 + z2) / 2;
-    ld hd = sqrtl((x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1) + (z2 - z1) * (z2 - z1)) / 2;
-    ld dist = sqrtl(cx * cx + cy * cy + cz * cz);
+    ld hd = sqrt((x2 - x1) * (x2 - x1) + (y2 - y1) * (y2 - y1) + (z2 - z1) * (z2 - z1)) / 2;
+    ld dist = sqrt(cx * cx + cy * cy + cz * cz);
     if (hd <= ratio * dist || depth >= 24) {
         gl_box(x1, x2, y1, y2, z1, z2, n, gx, gw, acc);
         return;
@@ -306,10 +312,10 @@ static int check_edges(int nz, const double *zedge)
 static void cell_bounds(int a, int b, int n, double dx, double dy, double dz, const double *zedge,
                         double h, ld bx[6])
 {
-    bx[0] = ((ld)a - 0.5L) * dx;
-    bx[1] = ((ld)a + 0.5L) * dx;
-    bx[2] = ((ld)b - 0.5L) * dy;
-    bx[3] = ((ld)b + 0.5L) * dy;
+    bx[0] = ((ld)a - (ld)0.5) * dx;
+    bx[1] = ((ld)a + (ld)0.5) * dx;
+    bx[2] = ((ld)b - (ld)0.5) * dy;
+    bx[3] = ((ld)b + (ld)0.5) * dy;
     bx[4] = (ld)h + layer_depth(n, dz, zedge);
     bx[5] = (ld)h + layer_depth(n + 1, dz, zedge);
 }
@@ -329,13 +335,13 @@ int orc_offset_kernels_z(double dx, double dy, double dz, const double *zedge, d
     ld gx[GL_MAX], gw[GL_MAX];
     gl_rule(8, gx, gw);
     ld tz = layer_depth(n + 1, dz, zedge) - layer_depth(n, dz, zedge);
-    ld hd = sqrtl((ld)dx * dx + (ld)dy * dy + tz * tz) / 2;
+    ld hd = sqrt((ld)dx * dx + (ld)dy * dy + tz * tz) / 2;
 #pragma omp parallel for schedule(dynamic, 64)
     for (int i = 0; i < count; ++i) {
         ld bx[6], o[NCOMP];
         cell_bounds(a[i], b[i], n, dx, dy, dz, zedge, h, bx);
         ld cx = (bx[0] + bx[1]) / 2, cy = (bx[2] + bx[3]) / 2, cz = (bx[4] + bx[5]) / 2;
-        ld dist = sqrtl(cx * cx + cy * cy + cz * cz);
+        ld dist = sqrt(cx * cx + cy * cy + cz * cz);
         if (mode == 1 && dist >= 24 * hd) {
             for (int c = 0; c < NCOMP; ++c) o[c] = 0;
             gl_box(bx[0], bx[1], bx[2], bx[3], bx[4], bx[5], 8, gx, gw, o);
@@ -363,9 +369,9 @@ int orc_offset_kernels(double dx, double dy, double dz, double h, int n, int cou
 static void fill_plane(ld *plane, int v0, int nxn, int w0, int nyn, double dx, double dy, ld z)
 {
     for (int jy = 0; jy < nyn; ++jy) {
-        ld y = ((ld)(w0 + jy) - 0.5L) * dy;
+        ld y = ((ld)(w0 + jy) - (ld)0.5) * dy;
         for (int ix = 0; ix < nxn; ++ix) {
-            ld x = ((ld)(v0 + ix) - 0.5L) * dx;
+            ld x = ((ld)(v0 + ix) - (ld)0.5) * dx;
             corner_terms(x, y, z, plane + ((size_t)jy * nxn + ix) * NCOMP);
         }
     }
@@ -550,7 +556,7 @@ int orc_dense_matrix(int nx, int ny, int nz, double dx, double dy, double dz, do
 #pragma omp parallel for schedule(dynamic, 1)
     for (long i = 0; i < nd; ++i) {
         int p = (int)(i % nx), q = (int)(i / nx);
-        ld sx = ((ld)p + 0.5L) * dx, sy = ((ld)q + 0.5L) * dy, sz = -(ld)h;
+        ld sx = ((ld)p + (ld)0.5) * dx, sy = ((ld)q + (ld)0.5) * dy, sz = -(ld)h;
         for (long j = 0; j < nm; ++j) {
             int l = (int)(j % nx), m = (int)((j / nx) % ny), n = (int)(j / ((long)nx * ny));
             ld o[NCOMP];
@@ -584,7 +590,7 @@ int orc_blocks_at_stations_z(int nx, int ny, int nz, double dx, double dy, doubl
     }
 #pragma omp parallel for schedule(dynamic, 16)
     for (int s = 0; s < nst; ++s) {
-        ld sx = ((ld)sp[s] + 0.5L) * dx, sy = ((ld)sq[s] + 0.5L) * dy, sz = -(ld)h;
+        ld sx = ((ld)sp[s] + (ld)0.5) * dx, sy = ((ld)sq[s] + (ld)0.5) * dy, sz = -(ld)h;
         ld acc[NCOMP] = {0};
         for (int k = 0; k < nblk; ++k) {
             const int *B = blk + 6 * k;

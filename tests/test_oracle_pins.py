@@ -466,3 +466,23 @@ def test_levels_forward_and_adjoint_compose(orc):
     assert abs(lhs - rhs) <= 1e-13 * np.linalg.norm(dg[:, comps]) * np.linalg.norm(r[:, comps])
     # level 0 is the single plane
     assert np.array_equal(d[0], orc.forward(g, m))
+
+
+def test_fp64_build_of_the_oracle(orc):
+    """The oracle's plain-double build (timed beside the long-double one) is
+    the same computation: it agrees to 1e-12 on the tiny grid, and on a wide
+    grid, where the closed forms' corner terms cancel over many orders, to
+    the 1e-8 its rounding allows (the long-double build is the reference)."""
+    g = Geometry(16, 16, 8, 50.0, 50.0, 50.0, 25.0)
+    rho = tiny_density(g.nx, g.ny, g.nz)
+    a = orc.forward(g, rho)
+    b = orc.forward_fp64(g, rho)
+    for c in range(orc.NCOMP):
+        assert rel(b[:, c], a[:, c]) <= 1e-12, c
+    w = Geometry(512, 512, 2, 20.0, 20.0, 20.0, 10.0)
+    rho = np.random.default_rng(3).uniform(-500, 500, size=(w.nz, w.ny, w.nx))
+    st = np.array([(0, 0), (256, 256)])
+    a = orc.forward(w, rho, st)
+    b = orc.forward_fp64(w, rho, st)
+    for c in range(orc.NCOMP):
+        assert rel(b[:, c], a[:, c]) <= 1e-8, c
