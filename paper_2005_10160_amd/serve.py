@@ -30,7 +30,6 @@ scheduler in real time, and ``bench_served`` replays a seeded Poisson trace.
 """
 
 import collections
-import heapq
 import itertools
 import threading
 import time
@@ -486,7 +485,6 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
            time_limit=None):
     """Replay arrivals in real time.  batched=False gives the plain baseline:
     one stream, FIFO, one model per call."""
-    from synth.trace import TraceRequest  # noqa: F401  (trace records)
     ex = executor_factory(n_slots if batched else 1)
     if batched:
         srv = Server(ex, budget_bytes, n_slots=n_slots, max_models=max_models, admit_timeout=None)
