@@ -563,7 +563,7 @@ gf_status gf_plan_create_levels(int nx, int ny, int nz, double dx, double dy, do
     if (s != GF_OK) return s;
     if (!(dz > 0) || !std::isfinite(dz)) return fail(GF_EINVAL, "cell sizes must be positive and finite");
     if (n_levels < 1) return fail(GF_EINVAL, "n_levels must be >= 1 (got %d)", n_levels);
-    if ((long)(nz + n_levels - 1) * nx * ny > (1L << 31)) return fail(GF_EUNSUPPORTED, "model too large");
+    if (((long)nz + n_levels - 1) * nx * ny > (1L << 31)) return fail(GF_EUNSUPPORTED, "model too large");
     const int nzs = nz + n_levels - 1;
     std::vector<double> edges(nzs + 1);
     for (int n = 0; n <= nzs; ++n) edges[n] = n * dz;

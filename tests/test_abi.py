@@ -113,3 +113,12 @@ def test_levels_plan_rejects_bad_arguments(lib, levels, dz, what):
                                    ctypes.byref(h))
     assert st == _native.GF_EINVAL, what
     assert h.value is None
+
+
+def test_levels_plan_rejects_oversize(lib):
+    from paper_2005_10160_amd import _native
+    h = ctypes.c_void_p()
+    st = lib.gf_plan_create_levels(1024, 1024, 100, 20.0, 20.0, 20.0, 10.0, 2147483600, ctypes.c_uint(0x1), 0, 0,
+                                   None, ctypes.byref(h))
+    assert st == _native.GF_EUNSUPPORTED
+    assert h.value is None
