@@ -398,3 +398,32 @@ def test_largest_grid(gf, orc, prec, mask):
         e = rel(gv, want[:, c])
         note("largest grid %s %s sampled rel %.2e" % (prec, NAMES[c], e))
         assert e <= tol, (NAMES[c], e)
+
+
+_PRISM_FIELDS = {}
+
+
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+@pytest.mark.parametrize("preset,n_prisms,seed", [("medium", 6, 202), ("paper_scale", 20, 302)])
+def test_prisms_full_field(gf, orc, preset, n_prisms, seed, prec, tol):
+    """The prism part of the medium and paper-scale models at every station:
+    the oracle integrates each prism as one merged block (its closed form,
+    pinned against the cell-by-cell sum), so the whole field costs one
+    evaluation per prism and station; all nine components against it."""
+    from synth.density import paint_prisms, random_prisms
+    g = PRESETS[preset]
+    prisms = random_prisms(g.nx, g.ny, g.nz, n_prisms, seed)
+    rho = paint_prisms(np.zeros((g.nz, g.ny, g.nx)), prisms)
+    key = (preset, n_prisms, seed)
+    if key not in _PRISM_FIELDS:
+        st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
+        note("prism field %s: oracle at all %d stations" % (preset, len(st)))
+        want = orc.blocks_at_stations(g, prisms, st)
+        _PRISM_FIELDS[key] = want.reshape(g.ny, g.nx, NC).transpose(2, 0, 1).copy()
+    want = _PRISM_FIELDS[key]
+    note("prism field %s %s: forward" % (preset, prec))
+    got = run_forward(gf, g, rho, mask=ALL9, prec=prec)
+    for c in range(NC):
+        e = rel(got[c], want[c])
+        note("prism field %s %s %s rel %.2e" % (preset, prec, NAMES[c], e))
+        assert e <= tol, (NAMES[c], e)
