@@ -123,3 +123,26 @@ def test_layered_paper_scale_sampled(gf, orc):
         e = rel(gv, want[:, c])
         note("layered paper scale %s sampled rel %.2e" % (NAMES[c], e))
         assert e <= TOL["f64"], NAMES[c]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_layered_paper_scale_prisms_full_field(gf, orc, prec):
+    """The 20 seeded prisms of the paper-scale model on the stretched mesh
+    (layers 5 m x 1.03^n), every station, all nine components, against the
+    oracle's merged-prism superposition through the layered depths."""
+    from synth.density import paint_prisms, random_prisms
+    g = PRESETS["paper_scale"]
+    z = stretched(g.nz, 0.0, 5.0, 1.03)
+    prisms = random_prisms(g.nx, g.ny, g.nz, 20, 302)
+    rho = paint_prisms(np.zeros((g.nz, g.ny, g.nx)), prisms)
+    st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
+    note("layered prism field: oracle at all %d stations" % len(st))
+    want = orc.blocks_at_stations(g, prisms, st, zedges=z).reshape(g.ny, g.nx, len(NAMES)).transpose(2, 0, 1)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    p = gf.plan_layered(g.nx, g.ny, g.dx, g.dy, z, g.h, ALL9, prec)
+    d = p.forward(torch.from_numpy(rho).to("cuda", dt)).double().cpu().numpy()
+    p.close()
+    for c in range(len(NAMES)):
+        e = rel(d[c], want[c])
+        note("layered prism field %s %s rel %.2e" % (prec, NAMES[c], e))
+        assert e <= TOL[prec], (NAMES[c], e)

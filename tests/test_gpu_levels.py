@@ -225,3 +225,25 @@ def test_autograd_through_level_and_layered_plans(gf, kind):
         want = p.adjoint((p.forward(m) - d_obs).contiguous())
     assert torch.equal(m.grad, want)
     p.close()
+
+
+def test_levels_medium_prisms_full_field(gf, orc):
+    """The medium model's six prisms under 64 observation levels (gz, six
+    levels a pass): every station of the lowest, a middle and the highest
+    level against the oracle's merged-prism superposition at the level's
+    height."""
+    from synth.density import paint_prisms, random_prisms
+    g = PRESETS["medium"]
+    levels = g.nz
+    prisms = random_prisms(g.nx, g.ny, g.nz, 6, 202)
+    rho = paint_prisms(np.zeros((g.nz, g.ny, g.nx)), prisms)
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, 0x1, "f64")
+    d = p.forward(torch.from_numpy(rho).cuda()).cpu().numpy()
+    p.close()
+    st = np.array([(q_, r_) for r_ in range(g.ny) for q_ in range(g.nx)])
+    for t in (0, levels // 2, levels - 1):
+        gt = Geometry(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz)
+        want = orc.blocks_at_stations(gt, prisms, st)[:, 0].reshape(g.ny, g.nx)
+        e = rel(d[t, 0], want)
+        note("levels prism field level %d gz rel %.2e" % (t, e))
+        assert e <= TOL["f64"], (t, e)
