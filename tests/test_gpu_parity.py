@@ -293,22 +293,23 @@ def test_dot_product(gf, prec, tol):
 
 
 # --------------------------------------------------------- full sizes ----
-def test_medium_grid_sampled_fp64(gf, orc):
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+def test_medium_grid_sampled(gf, orc, prec, tol):
     """256x256x64, 25x25x20 m cells, h = 10 m: prisms plus a Gaussian random
     field; sampled stations against the direct sum."""
     from synth import prisms_and_grf
     g = PRESETS["medium"]
     rho = prisms_and_grf(g.nx, g.ny, g.nz, 6, 202, 203)
-    note("medium grid: forward")
-    got = run_forward(gf, g, rho)
+    note("medium grid %s: forward" % prec)
+    got = run_forward(gf, g, rho, prec=prec)
     st = sample_stations(g.nx, g.ny, 7, seed=204)
     note("medium grid: oracle at %d stations" % len(st))
     want = orc.forward(g, rho, st)
     for c in range(NC):
         gv = got[c][st[:, 1], st[:, 0]]
         e = rel(gv, want[:, c])
-        note("medium fp64 %s sampled rel %.2e" % (NAMES[c], e))
-        assert e <= TOL64, NAMES[c]
+        note("medium %s %s sampled rel %.2e" % (prec, NAMES[c], e))
+        assert e <= tol, NAMES[c]
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
