@@ -1,8 +1,10 @@
 """Serving loop for the fast gravity operator: continuous batching over HIP
 streams with a geometry-keyed cache of resident kernel spectra.
 
-Requests carry a geometry (nx, ny, nz, dx, dy, dz, h, components), an
-operation (forward d = G rho or adjoint g = G^T r) and 1..B models.  The
+Requests carry a geometry (nx, ny, nz, dx, dy, dz, h, components, and
+optionally the layer edges of a layered mesh or a number of observation
+levels), an operation (forward d = G rho or adjoint g = G^T r) and 1..B
+models.  The
 kernel spectra of a geometry are built once (the geometry/density split of
 section 2.2: the kernel does not change between calls) and stay resident
 while memory allows.
