@@ -428,3 +428,23 @@ def test_prisms_full_field(gf, orc, preset, n_prisms, seed, prec, tol):
         e = rel(got[c], want[c])
         note("prism field %s %s %s rel %.2e" % (preset, prec, NAMES[c], e))
         assert e <= tol, (NAMES[c], e)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_components_vanishing_on_a_single_row_or_column(gf, orc, prec):
+    """One column of cells (nx = 1) puts every station on the x-symmetry
+    plane of every cell: gx, gxy, gxz vanish identically, and the library
+    returns exact zeros; one row (ny = 1) likewise for gy, gxy, gyz.  The
+    other components still match the oracle."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    tol = TOL64 if prec == "f64" else TOL32
+    for g, odd in ((Geometry(1, 40, 5, 20.0, 25.0, 15.0, 7.0), ("gx", "gxy", "gxz")),
+                   (Geometry(40, 1, 5, 20.0, 25.0, 15.0, 7.0), ("gy", "gxy", "gyz"))):
+        rho = tiny_density(g.nx, g.ny, g.nz, seed=91, block=None)
+        got = run_forward(gf, g, rho, mask=ALL9, prec=prec)
+        want = orc.forward_grid(g, rho)
+        for c, name in enumerate(NAMES):
+            if name in odd:
+                assert np.count_nonzero(got[c]) == 0, name
+            else:
+                assert rel(got[c], want[c]) <= tol, (g, name)
