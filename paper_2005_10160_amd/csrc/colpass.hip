@@ -476,11 +476,23 @@ struct WsCfg {
     static constexpr int TWW = up(2 * FFT::stw_entries());            // stage twiddles, shared
     static constexpr int QP = up(N / 2 + 1);                          // padded spectrum row
     static constexpr int CW = N;                                      // one column buffer (N/2 complex)
-    // T words per column: two spectrum buffers, two column buffers and the
+    // T words per column: nbuf spectrum buffers, two column buffers and the
     // waves' exchange arrays.  At the end, the first 2N words (re, im of N
     // values) hold the combination of the waves' inverse transforms.
-    static constexpr int group_words(int cmax) { return 2 * cmax * QP + 2 * CW + NW * XW; }
-    static constexpr size_t lds_bytes(int cmax) { return ((size_t)G * group_words(cmax) + TWW) * sizeof(T); }
+    static constexpr int words_with(int nbuf, int cmax) { return nbuf * cmax * QP + 2 * CW + NW * XW; }
+    static constexpr size_t bytes_with(int nbuf, int cmax)
+    {
+        return ((size_t)G * words_with(nbuf, cmax) + TWW) * sizeof(T);
+    }
+    // Two spectrum buffers (the next layer's rows stream in while this layer
+    // is reduced) unless only one fits in the 160 KB of LDS of a CU: FP64 at
+    // length 4096 holds three spectra with one buffer, one with two.  With
+    // one buffer the next layer's rows stream in while the next column is
+    // transformed.
+    static constexpr bool single_spec(int cmax) { return bytes_with(2, cmax) > 163840 && bytes_with(1, cmax) <= 163840; }
+    static constexpr int spec_bufs(int cmax) { return single_spec(cmax) ? 1 : 2; }
+    static constexpr int group_words(int cmax) { return words_with(spec_bufs(cmax), cmax); }
+    static constexpr size_t lds_bytes(int cmax) { return bytes_with(spec_bufs(cmax), cmax); }
     // register target: waves per SIMD of the workgroups that fit in 160 KB of LDS
     static constexpr int WG_PER_CU = (int)(163840 / lds_bytes(6)) > 0 ? (int)(163840 / lds_bytes(6)) : 1;
     static constexpr int WAVES_PER_EU = (THREADS >= 256 ? THREADS / 256 : 1) * WG_PER_CU;
@@ -778,11 +790,12 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned g = wv / NW, w = wv % NW;
     const unsigned tg = threadIdx.x - g * GT;
+    constexpr int NB = C::spec_bufs(CMAX);
     T *twq = lds;
     T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
-    T *sbuf = gb;                                                        // 2 x CMAX x QP
-    cx<T> *cbuf = reinterpret_cast<cx<T> *>(gb + 2 * CMAX * QP);         // 2 x N/2 complex
-    T *xch = gb + 2 * CMAX * QP + 2 * C::CW + w * C::XW;
+    T *sbuf = gb;                                                        // NB x CMAX x QP
+    cx<T> *cbuf = reinterpret_cast<cx<T> *>(gb + NB * CMAX * QP);        // 2 x N/2 complex
+    T *xch = gb + NB * CMAX * QP + 2 * C::CW + w * C::XW;
     const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
     F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
     for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) {
@@ -814,20 +827,26 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
         for (int s = 0; s < PPT; ++s) acc[c][s] = cx<T>{T(0), T(0)};
 
     cx<T> tail{T(0), T(0)};
-    auto stage = [&](int n, int buf) {
+    auto stage_spec = [&](int n, int buf) {
         stage_rows<T, GT, true>(spec + (size_t)n * layer_vals + (size_t)row * Cs * QP, sbuf + buf * CMAX * QP,
                                 (unsigned)Cs * QP, tg);
+    };
+    auto stage_col = [&](int n, int buf) {
         stage_column<T, GT>(column(R, (size_t)un.b * nz + n, M, un.u, ldc), cbuf + buf * (N / 2), ny, tg, tail);
     };
     if (n0 < n1) {
-        stage(n0, 0);
+        stage_spec(n0, 0);
+        stage_col(n0, 0);
         put_tail(cbuf, ny, tg, tail);
     }
     stage_wait<true>();
 
     for (int n = n0; n < n1; ++n) {
         const int cur = (n - n0) & 1;
-        if (n + 1 < n1) stage(n + 1, cur ^ 1);
+        if (n + 1 < n1) {
+            if constexpr (NB == 2) stage_spec(n + 1, cur ^ 1);
+            stage_col(n + 1, cur ^ 1);
+        }
         cx<T> v[PPT];
         const cx<T> *xc = cbuf + cur * (N / 2);
         if (un.part == 0)
@@ -837,14 +856,22 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
         else
             form_z<F, T, N, NW, L, PPT, 2>(v, xc, lane, w, cn, tws);
         F::template run<false>(v, xch, nullptr, lane, twp, twlog);
-        const T *scur = sbuf + cur * CMAX * QP;
+        // one buffer: this layer's spectrum rows (staged after the previous
+        // reduction) and the next column have landed
+        if constexpr (NB == 1) stage_wait<true>();
+        const T *scur = sbuf + (NB == 2 ? cur : 0) * CMAX * QP;
 #pragma unroll
         for (int c = 0; c < CMAX; ++c)
             if (c < Cs)
                 mac_ws_dispatch<F, T, PPT, NW, false>(acc[c], v, scur + c * QP, lane, lo, hi, (im_m >> c) & 1u,
                                                       (yo_m >> c) & 1u);
         if (n + 1 < n1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
-        stage_wait<true>();
+        if constexpr (NB == 2) {
+            stage_wait<true>();
+        } else {
+            lds_barrier();   // every wave is past its reads of the spectrum rows
+            if (n + 1 < n1) stage_spec(n + 1, 0);
+        }
     }
 
     // every wave is past its last reads of the staged buffers: the first 2N
@@ -898,6 +925,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     const unsigned tg = threadIdx.x - g * GT;
     T *twq = lds;
     T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
+    static_assert(C::spec_bufs(CMAX) == 2, "the spectral-layer ring takes both spectrum buffers");
     T *sbuf = gb;                                                        // ring: (nlev + 1) x Cs x QP <= 2 x CMAX x QP
     cx<T> *cbuf = reinterpret_cast<cx<T> *>(gb + 2 * CMAX * QP);         // 2 x N/2 complex
     T *xch = gb + 2 * CMAX * QP + 2 * C::CW + w * C::XW;
@@ -1017,12 +1045,15 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const unsigned g = wv / NW, w = wv % NW;
     const unsigned tg = threadIdx.x - g * GT;
+    constexpr int NB = C::spec_bufs(CMAX);
+    // the Cs residual columns (setup only) fit the spectrum and combination areas
+    static_assert(CMAX * N <= NB * CMAX * QP + 2 * C::CW, "residual columns exceed their staging area");
     T *twq = lds;
     T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
-    T *sbuf = gb;                                                        // 2 x CMAX x QP
-    T *cre = gb + 2 * CMAX * QP;                                         // combination: 2N words
+    T *sbuf = gb;                                                        // NB x CMAX x QP
+    T *cre = gb + NB * CMAX * QP;                                        // combination: 2N words
     cx<T> *rbuf = reinterpret_cast<cx<T> *>(gb);                         // residual columns (setup only)
-    T *xch = gb + 2 * CMAX * QP + 2 * C::CW + w * C::XW;
+    T *xch = gb + NB * CMAX * QP + 2 * C::CW + w * C::XW;
     const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
     F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
 
@@ -1043,7 +1074,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     const int n0 = un.n0;
     const int n1 = un.n1;
 
-    // residual columns into the spectrum area (Cs x N/2 complex fit in 2 x CMAX x QP words)
+    // residual columns into the spectrum (and, with one spectrum buffer, the
+    // combination) area
 #pragma unroll
     for (int c = 0; c < CMAX; ++c) {
         if (c < Cs) {
@@ -1077,10 +1109,12 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 
     for (int n = n0; n < n1; ++n) {
         const int cur = (n - n0) & 1;
-        if (n + 1 < n1)
-            stage_rows<T, GT, true>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
-                                    sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, tg);
-        const T *scur = sbuf + cur * CMAX * QP;
+        if constexpr (NB == 2) {
+            if (n + 1 < n1)
+                stage_rows<T, GT, true>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP,
+                                        sbuf + (cur ^ 1) * CMAX * QP, (unsigned)Cs * QP, tg);
+        }
+        const T *scur = sbuf + (NB == 2 ? cur : 0) * CMAX * QP;
         cx<T> v[PPT];
 #pragma unroll
         for (int s = 0; s < PPT; ++s) v[s] = cx<T>{T(0), T(0)};
@@ -1089,6 +1123,14 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             if (c < Cs)
                 mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[c], scur + c * QP, lane, lo, hi, (im_m >> c) & 1u,
                                                      (yo_m >> c) & 1u);
+        if constexpr (NB == 1) {
+            // one buffer: the next layer's rows stream in during this
+            // layer's inverse transform, once every wave is past its reads
+            lds_barrier();
+            if (n + 1 < n1)
+                stage_rows<T, GT, true>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP, sbuf,
+                                        (unsigned)Cs * QP, tg);
+        }
         ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre);
         lds_barrier();
         if (un.active)
@@ -1125,6 +1167,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     const unsigned tg = threadIdx.x - g * GT;
     T *twq = lds;
     T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
+    static_assert(C::spec_bufs(CMAX) == 2, "the spectral-layer ring takes both spectrum buffers");
     T *sbuf = gb;                                                        // ring: (nlev + 1) x Cs x QP <= 2 x CMAX x QP
     T *cre = gb + 2 * CMAX * QP;                                         // combination: 2N words
     cx<T> *rbuf = reinterpret_cast<cx<T> *>(gb);                         // residual columns (setup only)

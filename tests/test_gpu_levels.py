@@ -184,10 +184,10 @@ def test_levels_blocked_passes(gf, orc, mask, prec):
 
 
 def test_levels_longest_columns_fp64(gf, orc):
-    """Column length 4096 in FP64 leaves LDS for one spectrum per launch:
-    levels run one per pass there (the several-level passes need six
-    spectrum rows), forward and adjoint, against the oracle and the dot
-    product."""
+    """Column length 4096 in FP64 leaves LDS for one buffer of three
+    spectrum rows: levels run one per pass there (the several-level passes
+    need two buffers of six), forward and adjoint, against the oracle and
+    the dot product."""
     g = Geometry(6, 2048, 2, 30.0, 10.0, 10.0, 5.0)
     levels = 3
     rho = tiny_density(g.nx, g.ny, g.nz, seed=59, block=None)

@@ -346,8 +346,9 @@ def test_transform_length_sweep(gf, orc, nx, ny, prec, tol):
     """Forward and adjoint at every row and column transform length against
     the direct sum at sampled stations (corners, centre, an off-centre
     station; nz = 3, all nine components).  The FP64 column pass of length
-    4096 holds one spectrum per launch in LDS: there the eight spectra run
-    as eight column-pass groups."""
+    4096 holds three spectra per launch in LDS, with one spectrum buffer:
+    there the eight spectra run as column-pass groups of three, three and
+    two."""
     g = Geometry(nx, ny, 3, 20.0, 25.0, 15.0, 7.0)
     rng = np.random.default_rng(nx * 7919 + ny)
     rho = rng.uniform(-500.0, 500.0, size=(g.nz, ny, nx))
@@ -382,8 +383,8 @@ def test_largest_grid(gf, orc, prec, mask):
     """nx = ny = 2048, the largest grid (circulant 4096 x 4096, row and
     column transforms of the longest lengths together), three layers: FP32
     with six components, FP64 with gz alone and FP64 with six components
-    (one spectrum per column-pass launch at this length) against the direct
-    sum at sampled stations."""
+    (column-pass groups of three spectra with one spectrum buffer at this
+    length) against the direct sum at sampled stations."""
     g = Geometry(2048, 2048, 3, 10.0, 10.0, 10.0, 5.0)
     rng = np.random.default_rng(2048)
     rho = rng.uniform(-500.0, 500.0, size=(g.nz, g.ny, g.nx))
