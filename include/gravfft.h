@@ -103,6 +103,11 @@ typedef struct {
     size_t internal_workspace_bytes;
     double plan_ms;        /* wall time of gf_plan_create (kernel table + FFTs) */
     int n_levels;          /* observation levels (1 unless gf_plan_create_levels) */
+    int col_groups;        /* column-pass launches per level of a forward apply:
+                              resident spectra in groups of at most six (three
+                              or one where LDS holds fewer at this column
+                              length), each group re-reading the row-
+                              transformed density                             */
 } gf_plan_info_t;
 
 /*

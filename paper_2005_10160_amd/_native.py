@@ -34,6 +34,7 @@ class PlanInfo(ctypes.Structure):
         ("spectra_bytes", ctypes.c_size_t), ("internal_workspace_bytes", ctypes.c_size_t),
         ("plan_ms", ctypes.c_double),
         ("n_levels", ctypes.c_int),
+        ("col_groups", ctypes.c_int),
     ]
 
 

@@ -598,6 +598,7 @@ gf_status gf_plan_get_info(const gf_plan *p, gf_plan_info_t *info)
     info->ny = p->ny;
     info->nz = p->nz;
     info->n_levels = p->nt;
+    info->col_groups = p->ngrp;
     info->px = p->px;
     info->py = p->py;
     info->n_out = p->n_out;

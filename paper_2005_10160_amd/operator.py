@@ -85,6 +85,7 @@ class Plan:
         self.nx, self.ny, self.nz = info.nx, info.ny, info.nz
         self.n_out = info.n_out
         self.n_levels = info.n_levels
+        self.col_groups = info.col_groups
         # one data plane per observation level
         self.data_shape = ((self.n_levels,) if self.n_levels > 1 else ()) + (self.n_out, self.ny, self.nx)
         self.out_components = tuple(COMPONENTS[i] for i in range(len(COMPONENTS)) if self.mask >> i & 1)

@@ -42,6 +42,26 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) == set(_native.EXPORTED)
 
 
+_CTYPES = {"int": ctypes.c_int, "unsigned": ctypes.c_uint, "size_t": ctypes.c_size_t, "double": ctypes.c_double}
+
+
+def test_plan_info_binding_matches_header():
+    """The binding's PlanInfo mirrors gf_plan_info_t field by field (names,
+    order, C types), so the library writes every field where the binding
+    reads it."""
+    from paper_2005_10160_amd import _native
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{(.*?)\}\s*gf_plan_info_t;", text, flags=re.S).group(1)
+    fields = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        ctype, names = decl.split(None, 1)
+        fields += [(n.strip(), _CTYPES[ctype]) for n in names.split(",")]
+    assert [(n, t) for n, t in _native.PlanInfo._fields_] == fields
+
+
 def test_status_strings(lib):
     from paper_2005_10160_amd import _native
     for s in range(6):

@@ -115,3 +115,20 @@ def test_calls_on_two_streams_overlap_safely(gf):
     for d, gg in outs:
         assert torch.equal(d, want_d) and torch.equal(gg, want_g)
     p.close()
+
+
+@pytest.mark.parametrize("ny,prec,mask,groups", [
+    (1024, "f64", 0x3F, 1),     # column length 2048: six spectra in one launch
+    (1024, "f64", 0x1FF, 2),    # eight spectra: six + two
+    (2048, "f32", 0x3F, 1),     # length 4096 in FP32: six fit
+    (2048, "f64", 0x3F, 2),     # length 4096 in FP64: one buffer of three, 3 + 3
+    (2048, "f64", 0x1FF, 3),    # 3 + 3 + 2
+    (2048, "f64", 0x181, 1),    # gz, gx, gy
+])
+def test_column_pass_groups(gf, ny, prec, mask, groups):
+    """The plan reports how many column-pass launches a forward apply takes:
+    spectra in groups of six, or of three where LDS holds one buffer of three
+    spectrum rows but not two (FP64 at column length 4096)."""
+    p = gf.plan(4, ny, 1, 20.0, 20.0, 20.0, 10.0, mask, prec)
+    assert p.col_groups == groups
+    p.close()
