@@ -57,21 +57,30 @@ struct RowCfgF {
     using FFT = BlockFFT<T, M, NT, RADIX, true, false, NT == 64>;
     static constexpr int W = FFT::lds_words();
     static constexpr int E = 256 / (int)sizeof(T);   // elements of one 256-byte bank row
-    static constexpr int tr_calc()
+    static constexpr int tr_with(int kb, int threads)
     {
         int tr = 64;
-        while (tr > 1 && (tr * (W + E) * (int)sizeof(T) > 40 * 1024 || tr * NT > 512)) tr /= 2;
+        while (tr > 1 && (tr * (W + E) * (int)sizeof(T) > kb * 1024 || tr * NT > threads)) tr /= 2;
         return tr;
     }
-    static constexpr int TR = tr_calc();
+    // Rows of length 4096 (M = 2048) take two waves each; there rows within
+    // 80 KB (one workgroup per CU) double the FP64 row group to four rows,
+    // whose transposed stores then cover 64-byte segments instead of 32
+    // (FP64 row pass 4.5 -> 3.2 ms at 2048 x 2048 x 100; FP32, already at
+    // four rows by the thread limit, was slower with eight).
+    static constexpr int TR0 = tr_with(40, 512);
+    static constexpr int TR = M >= 2048 ? tr_with(80, 512) : TR0;
     static constexpr int THREADS = TR * NT;
     // row stride = E/TR mod E: the transposed reads (TR rows x E/TR units per
     // bank cycle) then fall in distinct banks
     static constexpr int SHIFT = E / TR > 0 ? E / TR : 1;
     static constexpr int WS = W + ((SHIFT - W % E) % E + E) % E;
     static constexpr int ROW_BYTES = WS * (int)sizeof(T);
-    // register target: waves per SIMD for two resident workgroups
-    static constexpr int WAVES_PER_EU = (2 * THREADS / 256) < 1 ? 1 : ((2 * THREADS / 256) > 8 ? 8 : 2 * THREADS / 256);
+    // register target: waves per SIMD for two resident workgroups (one for
+    // the larger row groups)
+    static constexpr int BPC = TR == TR0 ? 2 : 1;
+    static constexpr int WAVES_PER_EU =
+        (BPC * THREADS / 256) < 1 ? 1 : ((BPC * THREADS / 256) > 8 ? 8 : BPC * THREADS / 256);
 };
 
 // Blocks in XCD-contiguous order: the hardware deals consecutive blocks to
