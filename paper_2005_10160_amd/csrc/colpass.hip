@@ -15,6 +15,8 @@
 // ky in [0,Py/2]: K^ is purely real (gz, gxx, gxy, gyy) or purely imaginary
 // (gxz, gyz), and K^(kx,-ky) = +-K^(kx,ky) with the sign of the component's
 // parity in y.
+#include <type_traits>
+
 #include "gf_fft.h"
 #include "gf_launch.h"
 
@@ -461,6 +463,179 @@ constexpr bool use_ws() { return N >= 256; }
 template <typename T, int N>
 constexpr int ws_waves() { return use_ws<N>() ? N / (64 * ws_ppt<T, N>()) : 1; }
 
+// In-register transform of one wave: 256 points, four a lane, radix 4
+// (gfx950 cross-lane moves instead of LDS exchanges).  The point index has
+// eight bits: a lane's register slot holds two, the lane index six.  Each
+// radix-4 stage works on the slot bits; between stages the slot bits trade
+// places with two lane bits: v_permlane32_swap / v_permlane16_swap for lane
+// bits 5 and 4, DPP for bits 3-0 (quad permutes, row mirrors, bank masks).
+// Forward (decimation in frequency, stages on index bits 7-6, 5-4, 3-2,
+// 1-0): slot s of lane l holds n = l + 64 s on input and
+// k = rev(l) + 64 s on output, rev(l) = l/16 + 4 ((l/4) mod 4) + 16 (l mod 4).
+// Inverse (unnormalised): input in the forward's output layout, the lane
+// bits traded in the reverse order, output m = l + 64 s.
+template <typename T>
+struct LaneFFT {
+    static constexpr int lds_words() { return 0; }
+    static constexpr int stw_entries() { return 0; }
+    static constexpr int elem_in(int s) { return s; }
+    static constexpr int elem_out(int s) { return s; }
+    __device__ static void load_stage_table(T *, const cx<T> *, int, unsigned, unsigned) {}
+};
+
+template <typename F>
+struct is_lane_fft { static constexpr bool value = false; };
+template <typename T>
+struct is_lane_fft<LaneFFT<T>> { static constexpr bool value = true; };
+
+// Lane index of the forward output position: slot s of lane l holds
+// frequency ws_out_lane(l) + 64 s.
+template <typename F>
+__device__ __forceinline__ unsigned ws_out_lane(unsigned l)
+{
+    if constexpr (is_lane_fft<F>::value) return (l >> 4) + 4u * ((l >> 2) & 3u) + 16u * (l & 3u);
+    else return l;
+}
+
+template <int CTRL, int BANK = 0xF>
+__device__ __forceinline__ unsigned dpp_word(unsigned old, unsigned x)
+{
+    return (unsigned)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, 0xF, BANK, false);
+}
+
+// Trade the register bit that tells a from b with lane bit B, for one
+// 32-bit word: afterwards a holds the values whose lane bit B was 0 (at
+// lane bit B = the old register bit), b those whose lane bit B was 1.
+// `hi` is lane bit B of this lane.
+template <int B>
+__device__ __forceinline__ void xswap(unsigned &a, unsigned &b, bool hi)
+{
+    if constexpr (B == 5) {
+        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else if constexpr (B == 4) {
+        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
+        a = r[0];
+        b = r[1];
+    } else if constexpr (B == 3) {
+        // lane l ^ 8 = row mirror (l ^ 15) of the half-row mirror (l ^ 7);
+        // lanes with bit 3 set are banks 2 and 3 of each row
+        const unsigned ta = dpp_word<0x141>(0u, a), tb = dpp_word<0x141>(0u, b);
+        const unsigned na = dpp_word<0x140, 0xC>(a, tb), nb = dpp_word<0x140, 0x3>(b, ta);
+        a = na;
+        b = nb;
+    } else if constexpr (B == 2) {
+        // lane l ^ 4 = half-row mirror (l ^ 7) of the quad reversal (l ^ 3);
+        // lanes with bit 2 set are banks 1 and 3
+        const unsigned ta = dpp_word<0x1B>(0u, a), tb = dpp_word<0x1B>(0u, b);
+        const unsigned na = dpp_word<0x141, 0xA>(a, tb), nb = dpp_word<0x141, 0x5>(b, ta);
+        a = na;
+        b = nb;
+    } else {
+        // lane l ^ 1 or l ^ 2 within the quad, then a select on the lane bit
+        constexpr int Q = B == 0 ? 0xB1 : 0x4E;
+        const unsigned pa = dpp_word<Q>(0u, a), pb = dpp_word<Q>(0u, b);
+        const unsigned na = hi ? pb : a, nb = hi ? b : pa;
+        a = na;
+        b = nb;
+    }
+}
+
+template <int B, typename T>
+__device__ __forceinline__ void cswap(cx<T> &a, cx<T> &b, bool hi)
+{
+    constexpr int NWD = (int)sizeof(cx<T>) / 4;
+    unsigned wa[NWD], wb[NWD];
+    __builtin_memcpy(wa, &a, sizeof(a));
+    __builtin_memcpy(wb, &b, sizeof(b));
+#pragma unroll
+    for (int i = 0; i < NWD; ++i) xswap<B>(wa[i], wb[i], hi);
+    __builtin_memcpy(&a, wa, sizeof(a));
+    __builtin_memcpy(&b, wb, sizeof(b));
+}
+
+// slot bits 0 and 1 <-> lane bits BL and BL + 1
+template <int BL, typename T>
+__device__ __forceinline__ void digit_swap(cx<T> (&v)[4], unsigned lane)
+{
+    const bool h0 = (lane >> BL) & 1u, h1 = (lane >> (BL + 1)) & 1u;
+    cswap<BL>(v[0], v[1], h0);
+    cswap<BL>(v[2], v[3], h0);
+    cswap<BL + 1>(v[0], v[2], h1);
+    cswap<BL + 1>(v[1], v[3], h1);
+}
+
+// radix-4 butterfly over the slots: output d in slot d
+template <bool INV, typename T>
+__device__ __forceinline__ void radix4_slots(cx<T> (&v)[4])
+{
+    const cx<T> a = add(v[0], v[2]), b = sub(v[0], v[2]), c = add(v[1], v[3]), d = sub(v[1], v[3]);
+    const cx<T> jd = INV ? cx<T>{-d.im, d.re} : cx<T>{d.im, -d.re};   // (+-i) d
+    v[0] = add(a, c);
+    v[2] = sub(a, c);
+    v[1] = add(b, jd);
+    v[3] = sub(b, jd);
+}
+
+// Stage twiddles of this lane, t[3 g + d - 1] for stage g and digit d = 1..3:
+// forward W_256^{l d}, W_64^{(l mod 16) d}, W_16^{(l mod 4) d}; inverse the
+// conjugates of W_256^{rev(l) d}, W_64^{(l/16 + 4 ((l/4) mod 4)) d},
+// W_16^{(l/16) d}.  `tw` holds W_{2^twlog}^j (twlog >= 8).
+template <bool INV, typename T>
+__device__ __forceinline__ void lane_twiddles(cx<T> *t, const cx<T> *__restrict__ tw, int twlog, unsigned lane)
+{
+    const unsigned sh = (unsigned)(twlog - 8);
+    const unsigned e0 = INV ? ws_out_lane<LaneFFT<T>>(lane) : lane;
+    const unsigned e1 = INV ? (lane >> 4) + 4u * ((lane >> 2) & 3u) : (lane & 15u);
+    const unsigned e2 = INV ? (lane >> 4) : (lane & 3u);
+#pragma unroll
+    for (unsigned d = 1; d < 4; ++d) {
+        t[d - 1] = tw[((e0 * d) & 255u) << sh];
+        t[2 + d] = tw[((4u * e1 * d) & 255u) << sh];
+        t[5 + d] = tw[((16u * e2 * d) & 255u) << sh];
+    }
+    if (INV) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) t[i] = conjg(t[i]);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void lane_twiddle_mul(cx<T> (&v)[4], const cx<T> *t, int g)
+{
+#pragma unroll
+    for (int d = 1; d < 4; ++d) v[d] = mul(v[d], t[3 * g + d - 1]);
+}
+
+template <bool INV, typename T>
+__device__ __forceinline__ void lane_fft(cx<T> (&v)[4], unsigned lane, const cx<T> *t)
+{
+    radix4_slots<INV>(v);
+    lane_twiddle_mul(v, t, 0);
+    if constexpr (INV) digit_swap<0>(v, lane);
+    else digit_swap<4>(v, lane);
+    radix4_slots<INV>(v);
+    lane_twiddle_mul(v, t, 1);
+    digit_swap<2>(v, lane);
+    radix4_slots<INV>(v);
+    lane_twiddle_mul(v, t, 2);
+    if constexpr (INV) digit_swap<4>(v, lane);
+    else digit_swap<0>(v, lane);
+    radix4_slots<INV>(v);
+}
+
+// The wave transform of the wave split: in registers for four points a lane,
+// else the LDS-exchange block transform (xch, twp: its exchange array and
+// stage table; ltw: the in-register transform's lane twiddles).
+template <bool INV, typename F, typename T, int PPT>
+__device__ __forceinline__ void ws_fft(cx<T> (&v)[PPT], T *xch, unsigned lane, const cx<T> *twp, int twlog,
+                                       const cx<T> *ltw)
+{
+    if constexpr (is_lane_fft<F>::value) lane_fft<INV>(v, lane, ltw);
+    else F::template run<INV>(v, xch, nullptr, lane, twp, twlog);
+}
+
 template <typename T, int N>
 struct WsCfg {
     static constexpr int PPT = ws_ppt<T, N>();
@@ -469,7 +644,9 @@ struct WsCfg {
     static constexpr int G = NW >= 4 ? 1 : 4 / NW;                    // columns per workgroup
     static constexpr int GT = 64 * NW;                                // threads per column
     static constexpr int THREADS = G * GT;
-    using FFT = BlockFFT<T, L, 64, (PPT >= 8 ? 8 : PPT), true, true, true>;
+    // four points a lane: the in-register transform; eight: LDS exchanges
+    static constexpr bool LANE = PPT == 4;
+    using FFT = typename std::conditional<LANE, LaneFFT<T>, BlockFFT<T, L, 64, (PPT >= 8 ? 8 : PPT), true, true, true>>::type;
     static constexpr int VEC = 16 / (int)sizeof(T);
     static constexpr int up(int x) { return ((x + VEC - 1) / VEC) * VEC; }
     static constexpr int XW = up(FFT::lds_words());                   // one wave's exchange array
@@ -649,10 +826,11 @@ __device__ __forceinline__ void mac_ws_dispatch(cx<T> (&acc)[PPT], const cx<T> (
 // (re at cre[w L + m'], im at cre[N + w L + m']).
 template <typename F, typename T, int N, int NW, int L, int PPT>
 __device__ __forceinline__ void ws_inverse_put(cx<T> (&v)[PPT], T *xch, const cx<T> *twp, int twlog, unsigned lane,
-                                               unsigned w, const WsTwiddles<T, N, PPT> &tws, T *cre)
+                                               unsigned w, const WsTwiddles<T, N, PPT> &tws, T *cre, const cx<T> *ltw)
 {
-    out_to_in<F, T, PPT>(v);
-    F::template run<true>(v, xch, nullptr, lane, twp, twlog);
+    // the in-register transform takes the forward's output layout as it is
+    if constexpr (!is_lane_fft<F>::value) out_to_in<F, T, PPT>(v);
+    ws_fft<true, F>(v, xch, lane, twp, twlog, ltw);
 #pragma unroll
     for (int s = 0; s < PPT; ++s) {
         const unsigned m = lane + 64u * F::elem_out(s);
@@ -813,6 +991,9 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
     unsigned lo, hi;
     ws_offsets<NW, L>(w, lo, hi);
+    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    cx<T> ltw[C::LANE ? 9 : 1];
+    if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
     const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
     const unsigned row = spec_row(un.uv, (unsigned)M);
@@ -855,7 +1036,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             form_z<F, T, N, NW, L, PPT, 1>(v, xc, lane, w, cn, tws);
         else
             form_z<F, T, N, NW, L, PPT, 2>(v, xc, lane, w, cn, tws);
-        F::template run<false>(v, xch, nullptr, lane, twp, twlog);
+        ws_fft<false, F>(v, xch, lane, twp, twlog, ltw);
         // one buffer: this layer's spectrum rows (staged after the previous
         // reduction) and the next column have landed
         if constexpr (NB == 1) stage_wait<true>();
@@ -863,7 +1044,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int c = 0; c < CMAX; ++c)
             if (c < Cs)
-                mac_ws_dispatch<F, T, PPT, NW, false>(acc[c], v, scur + c * QP, lane, lo, hi, (im_m >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, false>(acc[c], v, scur + c * QP, ol, lo, hi, (im_m >> c) & 1u,
                                                       (yo_m >> c) & 1u);
         if (n + 1 < n1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
         if constexpr (NB == 2) {
@@ -877,10 +1058,11 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     // every wave is past its last reads of the staged buffers: the first 2N
     // words of the group's area take the waves' inverse transforms
     T *cre = gb;
+    if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
 #pragma unroll
     for (int c = 0; c < CMAX; ++c) {
         if (c < Cs) {
-            ws_inverse_put<F, T, N, NW, L, PPT>(acc[c], xch, twp, twlog, lane, w, tws, cre);
+            ws_inverse_put<F, T, N, NW, L, PPT>(acc[c], xch, twp, twlog, lane, w, tws, cre, ltw);
             lds_barrier();
             if (un.active) {
                 if (un.nyq)   // real partial column of the Nyquist unit
@@ -946,6 +1128,9 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
     unsigned lo, hi;
     ws_offsets<NW, L>(w, lo, hi);
+    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    cx<T> ltw[C::LANE ? 9 : 1];
+    if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
     const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
     const unsigned row = spec_row(un.uv, (unsigned)M);
@@ -989,13 +1174,13 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             form_z<F, T, N, NW, L, PPT, 1>(v, xc, lane, w, cn, tws);
         else
             form_z<F, T, N, NW, L, PPT, 2>(v, xc, lane, w, cn, tws);
-        F::template run<false>(v, xch, nullptr, lane, twp, twlog);
+        ws_fft<false, F>(v, xch, lane, twp, twlog, ltw);
 #pragma unroll
         for (int k = 0; k < CMAX; ++k)
             if (k < nk) {
                 const int j = k / Cs, c = k - j * Cs;
                 const T *srow = sbuf + (size_t)((n + j) % ring) * rowvals + (size_t)c * QP;
-                mac_ws_dispatch<F, T, PPT, NW, false>(acc[k], v, srow, lane, lo, hi, (imag_mask >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, false>(acc[k], v, srow, ol, lo, hi, (imag_mask >> c) & 1u,
                                                       (yodd_mask >> c) & 1u);
             }
         if (n + 1 < n1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
@@ -1003,10 +1188,11 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
 
     T *cre = gb;
+    if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
 #pragma unroll
     for (int k = 0; k < CMAX; ++k) {
         if (k < nk) {
-            ws_inverse_put<F, T, N, NW, L, PPT>(acc[k], xch, twp, twlog, lane, w, tws, cre);
+            ws_inverse_put<F, T, N, NW, L, PPT>(acc[k], xch, twp, twlog, lane, w, tws, cre, ltw);
             lds_barrier();
             if (un.active) {
                 if (un.nyq)
@@ -1067,6 +1253,9 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
     unsigned lo, hi;
     ws_offsets<NW, L>(w, lo, hi);
+    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    cx<T> ltw[C::LANE ? 9 : 1];
+    if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
     const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
     const unsigned row = spec_row(un.uv, (unsigned)M);
@@ -1099,10 +1288,11 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
                 form_z<F, T, N, NW, L, PPT, 1>(rh[c], xc, lane, w, cn, tws);
             else
                 form_z<F, T, N, NW, L, PPT, 2>(rh[c], xc, lane, w, cn, tws);
-            F::template run<false>(rh[c], xch, nullptr, lane, twp, twlog);
+            ws_fft<false, F>(rh[c], xch, lane, twp, twlog, ltw);
         }
     }
     lds_barrier();   // every wave is past its reads of the residual columns
+    if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
 
     if (n0 < n1) stage_rows<T, GT, true>(spec + (size_t)n0 * layer_vals + (size_t)row * Cs * QP, sbuf, (unsigned)Cs * QP, tg);
     stage_wait<true>();
@@ -1121,7 +1311,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int c = 0; c < CMAX; ++c)
             if (c < Cs)
-                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[c], scur + c * QP, lane, lo, hi, (im_m >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[c], scur + c * QP, ol, lo, hi, (im_m >> c) & 1u,
                                                      (yo_m >> c) & 1u);
         if constexpr (NB == 1) {
             // one buffer: the next layer's rows stream in during this
@@ -1131,7 +1321,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
                 stage_rows<T, GT, true>(spec + (size_t)(n + 1) * layer_vals + (size_t)row * Cs * QP, sbuf,
                                         (unsigned)Cs * QP, tg);
         }
-        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre);
+        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre, ltw);
         lds_barrier();
         if (un.active)
             ws_store<T, N, NW, L, PPT, GT>(cre, Gout + (((size_t)un.b * nz + n) * M + un.u) * (size_t)ldc, tg, ny,
@@ -1185,6 +1375,9 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
     unsigned lo, hi;
     ws_offsets<NW, L>(w, lo, hi);
+    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    cx<T> ltw[C::LANE ? 9 : 1];
+    if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
     const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
     const unsigned row = spec_row(un.uv, (unsigned)M);
@@ -1219,10 +1412,11 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
                 form_z<F, T, N, NW, L, PPT, 1>(rh[k], xc, lane, w, cn, tws);
             else
                 form_z<F, T, N, NW, L, PPT, 2>(rh[k], xc, lane, w, cn, tws);
-            F::template run<false>(rh[k], xch, nullptr, lane, twp, twlog);
+            ws_fft<false, F>(rh[k], xch, lane, twp, twlog, ltw);
         }
     }
     lds_barrier();   // every wave is past its reads of the residual columns
+    if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
 
     auto stage_spec = [&](int sl) {
         stage_rows<T, GT, true>(spec + (size_t)sl * layer_vals + (size_t)row * rowvals,
@@ -1242,10 +1436,10 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             if (k < nk) {
                 const int j = k / Cs, c = k - j * Cs;
                 const T *srow = sbuf + (size_t)((n + j) % ring) * rowvals + (size_t)c * QP;
-                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[k], srow, lane, lo, hi, (imag_mask >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[k], srow, ol, lo, hi, (imag_mask >> c) & 1u,
                                                      (yodd_mask >> c) & 1u);
             }
-        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre);
+        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre, ltw);
         lds_barrier();
         if (un.active)
             ws_store<T, N, NW, L, PPT, GT>(cre, Gout + (((size_t)un.b * nz + n) * M + un.u) * (size_t)ldc, tg, ny,
