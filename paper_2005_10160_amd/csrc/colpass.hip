@@ -468,7 +468,7 @@ constexpr int ws_waves() { return use_ws<N>() ? N / (64 * ws_ppt<T, N>()) : 1; }
 // eight bits: a lane's register slot holds two, the lane index six.  Each
 // radix-4 stage works on the slot bits; between stages the slot bits trade
 // places with two lane bits: v_permlane32_swap / v_permlane16_swap for lane
-// bits 5 and 4, DPP for bits 3-0 (quad permutes, row mirrors, bank masks).
+// bits 5 and 4, DPP for bits 3-0 (bank-masked row shifts, quad permutes).
 // Forward (decimation in frequency, stages on index bits 7-6, 5-4, 3-2,
 // 1-0): slot s of lane l holds n = l + 64 s on input and
 // k = rev(l) + 64 s on output, rev(l) = l/16 + 4 ((l/4) mod 4) + 16 (l mod 4).
@@ -518,18 +518,14 @@ __device__ __forceinline__ void xswap(unsigned &a, unsigned &b, bool hi)
         const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
         a = r[0];
         b = r[1];
-    } else if constexpr (B == 3) {
-        // lane l ^ 8 = row mirror (l ^ 15) of the half-row mirror (l ^ 7);
-        // lanes with bit 3 set are banks 2 and 3 of each row
-        const unsigned ta = dpp_word<0x141>(0u, a), tb = dpp_word<0x141>(0u, b);
-        const unsigned na = dpp_word<0x140, 0xC>(a, tb), nb = dpp_word<0x140, 0x3>(b, ta);
-        a = na;
-        b = nb;
-    } else if constexpr (B == 2) {
-        // lane l ^ 4 = half-row mirror (l ^ 7) of the quad reversal (l ^ 3);
-        // lanes with bit 2 set are banks 1 and 3
-        const unsigned ta = dpp_word<0x1B>(0u, a), tb = dpp_word<0x1B>(0u, b);
-        const unsigned na = dpp_word<0x141, 0xA>(a, tb), nb = dpp_word<0x141, 0x5>(b, ta);
+    } else if constexpr (B == 3 || B == 2) {
+        // row shifts by 2^B written only to the banks (groups of four lanes)
+        // whose lane bit B is set (a: from lane l - 2^B of b) or clear (b:
+        // from lane l + 2^B of a): banks 2, 3 / 0, 1 for bit 3, 1, 3 / 0, 2
+        // for bit 2
+        constexpr int SHR = 0x110 + (1 << B), SHL = 0x100 + (1 << B);
+        constexpr int SET = B == 3 ? 0xC : 0xA, CLR = B == 3 ? 0x3 : 0x5;
+        const unsigned na = dpp_word<SHR, SET>(a, b), nb = dpp_word<SHL, CLR>(b, a);
         a = na;
         b = nb;
     } else {
