@@ -865,10 +865,56 @@ __device__ __forceinline__ cx<T> ws_combine_j(const T *cre, unsigned mp, unsigne
 // y = tg + GT q, q < (N/2)/GT (consecutive threads, consecutive rows).
 // part: 0 complex column, 1 / 2 the real / imaginary field of a packed
 // column, 3 a real column (array of T).
+// ws_combine from the NW values of one m' already in registers (the same
+// sum, in the same order).
+template <typename T, int NW, int J, int WI = 0>
+__device__ __forceinline__ cx<T> ws_combine_regs(const cx<T> (&a)[NW])
+{
+    if constexpr (WI == NW) {
+        return cx<T>{T(0), T(0)};
+    } else {
+        return add(wpow<T, -J * WI, NW>(a[WI]), ws_combine_regs<T, NW, J, WI + 1>(a));
+    }
+}
+
+template <typename T, int NW, int JJ = 0>
+__device__ __forceinline__ cx<T> ws_combine_regs_j(const cx<T> (&a)[NW], unsigned j)
+{
+    if constexpr (JJ + 1 >= NW / 2) {
+        return ws_combine_regs<T, NW, JJ>(a);
+    } else {
+        if (j == (unsigned)JJ) return ws_combine_regs<T, NW, JJ>(a);
+        return ws_combine_regs_j<T, NW, JJ + 1>(a, j);
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ void ws_put(cx<T> *dst, unsigned y, const cx<T> &r, int part)
+{
+    if (part == 0)
+        dst[y] = r;
+    else if (part == 3)
+        reinterpret_cast<T *>(dst)[y] = r.re;
+    else
+        reinterpret_cast<T *>(dst)[2 * y + (part - 1)] = r.re;
+}
+
 template <typename T, int N, int NW, int L, int PPT, int GT, int Q = 0>
 __device__ __forceinline__ void ws_store(const T *cre, cx<T> *dst, unsigned tg, int ny, int part)
 {
-    if constexpr (Q < (N / 2) / GT) {
+    if constexpr (Q == 0 && NW > 1 && GT % L == 0 && (N / 2) / GT > 1) {
+        // every output row of this thread has the same m' = tg mod L (rows
+        // GT apart, GT a multiple of L): read the NW wave values once
+        const unsigned mp = tg % (unsigned)L, j0 = tg / (unsigned)L;
+        cx<T> a[NW];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) a[w] = cx<T>{cre[w * L + mp], cre[N + w * L + mp]};
+#pragma unroll
+        for (int q = 0; q < (N / 2) / GT; ++q) {
+            const unsigned y = tg + (unsigned)(GT * q);
+            if (y < (unsigned)ny) ws_put(dst, y, ws_combine_regs_j<T, NW>(a, j0 + (unsigned)(q * (GT / L))), part);
+        }
+    } else if constexpr (Q < (N / 2) / GT) {
         const unsigned y = tg + (unsigned)(GT * Q);
         if (y < (unsigned)ny) {
             const unsigned j = y / (unsigned)L;
