@@ -486,3 +486,94 @@ def test_fp64_build_of_the_oracle(orc):
     b = orc.forward_fp64(w, rho, st)
     for c in range(orc.NCOMP):
         assert rel(b[:, c], a[:, c]) <= 1e-8, c
+
+
+# --------------------------------------------------------------- pin 15 ----
+def _cell_box(g, a, b, n):
+    """Bounds of the cell at offset (a, b) in layer n relative to its station
+    (source minus station, z down): the geometry of section 2.1 with the
+    stations above the cell centres."""
+    return ((a - 0.5) * g.dx, (a + 0.5) * g.dx, (b - 0.5) * g.dy, (b + 0.5) * g.dy,
+            g.h + n * g.dz, g.h + (n + 1) * g.dz)
+
+
+def _offsets_in_shell(g, n, lo, hi, count, seed):
+    """Offsets (a, b) of layer n whose cell centre lies between lo and hi
+    half-diagonals from the station."""
+    rng = np.random.default_rng(seed)
+    s = np.sqrt(g.dx ** 2 + g.dy ** 2 + g.dz ** 2) / 2
+    zc = g.h + (n + 0.5) * g.dz
+    out = []
+    while len(out) < count:
+        dist = rng.uniform(lo, hi) * s
+        if dist <= zc:
+            continue
+        rxy = np.sqrt(dist ** 2 - zc ** 2)
+        phi = rng.uniform(0, 2 * np.pi)
+        a, b = int(round(rxy * np.cos(phi) / g.dx)), int(round(rxy * np.sin(phi) / g.dy))
+        c = np.sqrt((a * g.dx) ** 2 + (b * g.dy) ** 2 + zc ** 2) / s
+        if lo <= c <= hi:
+            out.append((a, b))
+    return np.array(out)
+
+
+def test_far_field_rule_of_the_offset_table(orc):
+    """The offset table's far-field branch (mode 1: one 8^3 Gauss-Legendre
+    rule over the cell beyond 24 half-diagonals) against two routes that do
+    not share it: the closed form (mode 0) from 24 to 100 half-diagonals,
+    where its cancellation still leaves ~1e-11, and an adaptive brute force
+    of another order and subdivision from 100 to 1000 half-diagonals."""
+    g = Geometry(1, 1, 6, 20.0, 30.0, 15.0, 10.0)
+    for n in (0, 3, 5):
+        ab = _offsets_in_shell(g, n, 24.0, 100.0, 40, seed=80 + n)
+        k1 = orc.offset_kernels(g, n, ab[:, 0], ab[:, 1], mode=1)
+        k0 = orc.offset_kernels(g, n, ab[:, 0], ab[:, 1], mode=0)
+        for i, (a, b) in enumerate(ab):
+            box = _cell_box(g, a, b, n)
+            tol = 1e-12 * cancellation_factor(box)
+            st = np.abs(k0[i][TENSOR]).max()
+            sg = np.abs(k0[i][[GZ, GX, GY]]).max()
+            assert np.all(np.abs(k1[i][TENSOR] - k0[i][TENSOR]) <= tol * st), (n, a, b)
+            assert np.all(np.abs(k1[i][[GZ, GX, GY]] - k0[i][[GZ, GX, GY]]) <= tol * sg), (n, a, b)
+        ab = _offsets_in_shell(g, n, 100.0, 1000.0, 12, seed=90 + n)
+        k1 = orc.offset_kernels(g, n, ab[:, 0], ab[:, 1], mode=1)
+        for i, (a, b) in enumerate(ab):
+            q = orc.prism_gl(*_cell_box(g, a, b, n), ratio=0.004, order=5)
+            st = np.abs(q[TENSOR]).max()
+            sg = np.abs(q[[GZ, GX, GY]]).max()
+            assert np.all(np.abs(k1[i][TENSOR] - q[TENSOR]) <= 1e-14 * st), (n, a, b)
+            assert np.all(np.abs(k1[i][[GZ, GX, GY]] - q[[GZ, GX, GY]]) <= 1e-14 * sg), (n, a, b)
+    # the full table switches branch inside it; both halves agree with mode 0
+    # where the closed form is still exact to its cancellation
+    gw = Geometry(40, 30, 2, 20.0, 30.0, 15.0, 10.0)
+    for n in range(gw.nz):
+        t1 = orc.kernel_table(gw, n, mode=1)
+        t0 = orc.kernel_table(gw, n, mode=0)
+        for c in range(orc.NCOMP):
+            s = np.abs(t0[c]).max()
+            assert np.abs(t1[c] - t0[c]).max() <= 1e-12 * s, (n, c)
+
+
+def test_levels_are_the_model_under_empty_layers(orc):
+    """Level t of the equal-dimension survey (stations t dz higher) is the
+    single-plane operator of a grid with t empty layers on top of the model,
+    forward and adjoint (superposition, eq. 3: empty cells add nothing).
+    dx, dy and dz all differ, so a level spacing taken from the wrong axis
+    fails here."""
+    g = Geometry(6, 5, 3, 20.0, 25.0, 15.0, 9.0)
+    levels = 4
+    rng = np.random.default_rng(63)
+    m = rng.standard_normal((g.nz, g.ny, g.nx)) * 300
+    d = orc.forward_levels(g, m, levels)                       # (levels, nst, NCOMP)
+    r = rng.standard_normal((levels, orc.NCOMP, g.ny, g.nx))
+    mask = 0x1BF                                               # all but gzz
+    gt = orc.adjoint_levels(g, r, mask, levels)
+    total = np.zeros_like(gt)
+    for t in range(levels):
+        big = Geometry(g.nx, g.ny, g.nz + t, g.dx, g.dy, g.dz, g.h)
+        mb = np.concatenate([np.zeros((t, g.ny, g.nx)), m])
+        want = orc.forward(big, mb)
+        for c in range(orc.NCOMP):
+            assert rel(d[t][:, c], want[:, c]) <= 1e-13, (t, c)
+        total += orc.adjoint(big, r[t], mask)[t:]
+    assert rel(gt, total) <= 1e-13
