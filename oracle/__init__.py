@@ -26,24 +26,35 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gravity_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "_gravity_oracle.so")
 _LIB64_PATH = os.path.join(_HERE, "_gravity_oracle_f64.so")
+_LIBSAN_PATH = os.path.join(_HERE, "_gravity_oracle_san.so")
 _lock = threading.Lock()
 _lib = None
 _lib64 = None
 
+# Set to "1" (before the first call) to load the build instrumented with the
+# address and undefined-behaviour sanitizers instead of the reference build;
+# the process must then start with the sanitizer runtime preloaded.
+SANITIZE_ENV = "GF_ORACLE_SANITIZE"
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
 
-def build(force=False):
+
+def build(force=False, sanitize=False):
     """Compile the oracle with gcc (no fast-math, no FMA contraction): the
     long-double reference and, from the same source, its plain-double build
-    (timed beside it, never a reference)."""
-    for path, extra in ((_LIB_PATH, []), (_LIB64_PATH, ["-DORC_FP64"])):
+    (timed beside it, never a reference).  sanitize=True builds only the
+    sanitizer-instrumented variant of the reference."""
+    opt = ["-O3", "-march=x86-64-v3"]
+    builds = ((_LIBSAN_PATH, SANITIZE_FLAGS),) if sanitize else ((_LIB_PATH, opt), (_LIB64_PATH, opt + ["-DORC_FP64"]))
+    for path, extra in builds:
         if not force and os.path.exists(path) and os.path.getmtime(path) >= os.path.getmtime(_SRC):
             continue
         tmp = path + ".tmp%d" % os.getpid()
-        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-               "-Wall"] + extra + ["-o", tmp, _SRC, "-lm"]
+        cmd = (["gcc"] + extra + ["-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-Wall",
+                                  "-o", tmp, _SRC, "-lm"])
         subprocess.run(cmd, check=True)
         os.replace(tmp, path)
-    return _LIB_PATH
+    return builds[0][0]
 
 
 def _load(fp64=False):
@@ -51,8 +62,11 @@ def _load(fp64=False):
     with _lock:
         if (_lib64 if fp64 else _lib) is not None:
             return _lib64 if fp64 else _lib
-        build()
-        lib = ctypes.CDLL(_LIB64_PATH if fp64 else _LIB_PATH)
+        if os.environ.get(SANITIZE_ENV) == "1" and not fp64:
+            lib = ctypes.CDLL(build(sanitize=True))
+        else:
+            build()
+            lib = ctypes.CDLL(_LIB64_PATH if fp64 else _LIB_PATH)
         d, i, u = ctypes.c_double, ctypes.c_int, ctypes.c_uint
         pd = ctypes.POINTER(ctypes.c_double)
         pi = ctypes.POINTER(ctypes.c_int)
@@ -78,6 +92,8 @@ def _load(fp64=False):
         lib.orc_forward_z.restype = i
         lib.orc_adjoint_z.argtypes = [i, i, i, d, d, d, pd, d, i, u, pd, i, pi, pi, pi, pd]
         lib.orc_adjoint_z.restype = i
+        lib.orc_forward_tab_z.argtypes = [i, i, i, d, d, d, pd, d, i, pd, u, i, pi, pi, pd]
+        lib.orc_forward_tab_z.restype = i
         lib.orc_blocks_at_stations_z.argtypes = [i, i, i, d, d, d, pd, d, i, pi, pd, i, pi, pi, pd]
         lib.orc_blocks_at_stations_z.restype = i
         lib.orc_max_threads.restype = i
@@ -221,6 +237,38 @@ def forward(geom, rho, stations=None, zedges=None, _fp64=False):
         rc = _load().orc_forward(*_geom(geom), nb, _pd(rho), int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
     if rc != 0:
         raise ValueError("oracle forward failed (%d)" % rc)
+    return out[0] if squeeze else out
+
+
+def forward_tabulated(geom, rho, stations=None, mask=0x3F, zedges=None):
+    """The direct sum of forward() (eq. 3) with each layer's kernel tabulated
+    once over all offsets (eq. 7, eq. 10) from the same closed form, then
+    summed by multiply-adds in the order: row sums over l, rows in ascending
+    m, layers in ascending n, all in long double.  Fast enough for every
+    station of a 256^2 x 64 grid or a thousand stations of a 1024^2 x 100
+    grid.  mask: components summed (bit c = COMPONENTS[c]); the others are 0.
+    Returns (nb, nst, NCOMP) (nb dropped for 3-D rho)."""
+    rho = np.asarray(rho, dtype=np.float64)
+    squeeze = rho.ndim == 3
+    if squeeze:
+        rho = rho[None]
+    nb = rho.shape[0]
+    assert rho.shape[1:] == (geom.nz, geom.ny, geom.nx), rho.shape
+    rho = np.ascontiguousarray(rho)
+    if stations is None:
+        qq, pp = np.meshgrid(np.arange(geom.ny), np.arange(geom.nx), indexing="ij")
+        stations = np.stack([pp.ravel(), qq.ravel()], axis=1)
+    st = np.ascontiguousarray(stations, dtype=np.int32).reshape(-1, 2)
+    sp = np.ascontiguousarray(st[:, 0])
+    sq = np.ascontiguousarray(st[:, 1])
+    out = np.zeros((nb, st.shape[0], NCOMP))
+    z = _edges(geom, zedges)
+    zp = ctypes.POINTER(ctypes.c_double)() if z is None else _pd(z)
+    nx, ny, nz, dx, dy, dz, h = _geom(geom)
+    rc = _load().orc_forward_tab_z(nx, ny, nz, dx, dy, dz, zp, h, nb, _pd(rho), ctypes.c_uint(int(mask)),
+                                   int(st.shape[0]), _pi(sp), _pi(sq), _pd(out))
+    if rc != 0:
+        raise ValueError("oracle tabulated forward failed (%d)" % rc)
     return out[0] if squeeze else out
 
 

@@ -293,43 +293,60 @@ def test_dot_product(gf, prec, tol):
 
 
 # --------------------------------------------------------- full sizes ----
+_TABULATED = {}
+
+
+def tabulated_oracle(orc, key, g, rho, st, mask):
+    """The oracle's tabulated direct sum (eq. 3 over each layer's offset
+    table), computed once per module for both precisions."""
+    if key not in _TABULATED:
+        import time
+        t0 = time.time()
+        note("%s: oracle tabulated sum at %d stations (%d threads)" % (key, len(st), orc.max_threads()))
+        _TABULATED[key] = orc.forward_tabulated(g, rho, st, mask=mask)
+        note("%s: oracle done in %.1f s" % (key, time.time() - t0))
+    return _TABULATED[key]
+
+
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
-def test_medium_grid_sampled(gf, orc, prec, tol):
-    """256x256x64, 25x25x20 m cells, h = 10 m: prisms plus a Gaussian random
-    field; sampled stations against the direct sum."""
+def test_medium_grid_every_station(gf, orc, prec, tol):
+    """256x256x64, 25x25x20 m cells, h = 10 m: the complete model (6 prisms
+    plus the Gaussian random field) at all 65 536 stations, all nine
+    components, against the oracle's tabulated direct sum."""
     from synth import prisms_and_grf
     g = PRESETS["medium"]
     rho = prisms_and_grf(g.nx, g.ny, g.nz, 6, 202, 203)
+    st = np.array([(p, q) for q in range(g.ny) for p in range(g.nx)])
+    want = tabulated_oracle(orc, "medium", g, rho, st, ALL9)
+    want = want.reshape(g.ny, g.nx, NC).transpose(2, 0, 1)
     note("medium grid %s: forward" % prec)
     got = run_forward(gf, g, rho, prec=prec)
-    st = sample_stations(g.nx, g.ny, 7, seed=204)
-    note("medium grid: oracle at %d stations" % len(st))
-    want = orc.forward(g, rho, st)
     for c in range(NC):
-        gv = got[c][st[:, 1], st[:, 0]]
-        e = rel(gv, want[:, c])
-        note("medium %s %s sampled rel %.2e" % (prec, NAMES[c], e))
+        e = rel(got[c], want[c])
+        note("medium %s %s every station rel %.2e" % (prec, NAMES[c], e))
         assert e <= tol, NAMES[c]
 
 
 @pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
-def test_paper_scale_sampled(gf, orc, prec, tol):
-    """1024x1024x100, 20 m cells, h = 10 m, 20 prisms plus a Gaussian random
-    field, in the launch configuration the benchmark times: sampled stations
-    (centre and corners) against the direct sum."""
+def test_paper_scale_1024_stations(gf, orc, prec, tol):
+    """1024x1024x100, 20 m cells, h = 10 m, the complete model (20 prisms plus
+    the Gaussian random field) in the launch configuration the benchmark
+    times (six components, batch 1): 1024 seeded stations (corners, edge
+    midpoints, centre and 1015 random ones) against the oracle's tabulated
+    direct sum."""
     from synth import prisms_and_grf
     g = PRESETS["paper_scale"]
     note("paper scale %s: density" % prec)
     rho = prisms_and_grf(g.nx, g.ny, g.nz, 20, 302, 303)
+    st = sample_stations(g.nx, g.ny, 1015, seed=303)
+    assert len(st) == 1024
+    want = tabulated_oracle(orc, "paper_scale", g, rho, st, 0x3F)
     note("paper scale %s: forward" % prec)
-    got = run_forward(gf, g, rho, mask=ALL9, prec=prec)
-    st = sample_stations(g.nx, g.ny, 0, seed=1)[[8, 0, 3]]
-    note("paper scale %s: oracle at %d stations" % (prec, len(st)))
-    want = orc.forward(g, rho, st)
-    for c in range(NC):
+    got = run_forward(gf, g, rho, mask=0x3F, prec=prec)
+    for c in range(6):
         gv = got[c][st[:, 1], st[:, 0]]
         e = rel(gv, want[:, c])
-        note("paper scale %s %s sampled rel %.2e" % (prec, NAMES[c], e))
+        note("paper scale %s %s at 1024 stations rel %.2e" % (prec, NAMES[c], e))
         assert e <= tol, NAMES[c]
 
 
