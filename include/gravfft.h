@@ -245,6 +245,20 @@ gf_status gf_debug_kernel_table(const gf_plan *plan, int n, double *host_out);
  * gravitational constant). */
 gf_status gf_debug_spectrum(const gf_plan *plan, unsigned component, int n, double *host_out);
 
+/*
+ * Failure injection, for tests of the error paths: the nth device
+ * allocation the library makes from now on (nth = 1: the next one) fails as
+ * if the device were out of memory, so that the call making it returns
+ * GF_ENOMEM; nth = 0 switches this off.  Process-wide, not thread-safe with
+ * respect to which call meets the failure.  Returns GF_EINVAL for nth < 0.
+ */
+gf_status gf_debug_fail_alloc(int nth);
+
+/* Bytes of device memory the library holds at this moment, over every plan
+ * of the process (spectra, twiddles, layer edges, internal workspaces, and
+ * plan-time scratch while a plan is being built). */
+size_t gf_debug_live_bytes(void);
+
 #ifdef __cplusplus
 }
 #endif

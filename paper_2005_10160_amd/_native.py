@@ -20,7 +20,7 @@ EXPORTED = (
     "gf_plan_create", "gf_plan_create_layered", "gf_plan_create_levels", "gf_plan_destroy", "gf_plan_get_info", "gf_plan_bytes",
     "gf_workspace_bytes", "gf_forward", "gf_adjoint", "gf_status_string",
     "gf_last_error", "gf_debug_kernel_table", "gf_debug_spectrum",
-    "gf_plan_set_timing", "gf_plan_last_pass_ms",
+    "gf_plan_set_timing", "gf_plan_last_pass_ms", "gf_debug_fail_alloc", "gf_debug_live_bytes",
 )
 
 
@@ -90,6 +90,10 @@ def load(path=None):
         lib.gf_plan_set_timing.restype = i
         lib.gf_plan_last_pass_ms.argtypes = [vp, i, pd]
         lib.gf_plan_last_pass_ms.restype = i
+        lib.gf_debug_fail_alloc.argtypes = [i]
+        lib.gf_debug_fail_alloc.restype = i
+        lib.gf_debug_live_bytes.argtypes = []
+        lib.gf_debug_live_bytes.restype = sz
         _lib = lib
         return lib
 

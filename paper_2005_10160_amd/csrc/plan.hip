@@ -7,7 +7,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "gf_launch.h"
@@ -90,12 +92,43 @@ gf::GLRules make_rules()
 bool is_imag(int code) { return code == 3 || code == 5 || code == 7 || code == 8; }   // odd in exactly one of x, y
 bool is_yodd(int code) { return code == 2 || code == 5 || code == 8; }                // odd in y
 
+// Every device allocation of the library goes through dev_malloc and
+// dev_free, which keep the bytes held (for tests that check that failed
+// calls leak nothing) and can be told to fail the n-th allocation from now
+// (gf_debug_fail_alloc).
+std::mutex g_alloc_mu;
+std::unordered_map<void *, size_t> g_live;
+size_t g_live_bytes = 0;
+long g_fail_countdown = 0;
+
+hipError_t dev_malloc(void **ptr, size_t bytes)
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    *ptr = nullptr;
+    if (g_fail_countdown > 0 && --g_fail_countdown == 0) return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipSuccess) {
+        g_live[*ptr] = bytes;
+        g_live_bytes += bytes;
+    }
+    return e;
+}
+
+void dev_free(void *ptr)
+{
+    if (!ptr) return;
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    auto it = g_live.find(ptr);
+    if (it != g_live.end()) {
+        g_live_bytes -= it->second;
+        g_live.erase(it);
+    }
+    (void)hipFree(ptr);
+}
+
 struct DevBuf {
     void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p) (void)hipFree(p);
-    }
+    ~DevBuf() { dev_free(p); }
 };
 
 }  // namespace
@@ -297,9 +330,9 @@ gf_status build_spectra(gf_plan *p, hipStream_t st)
     if (nl > p->nzs) nl = p->nzs;
     DevBuf E, Rk;
     gf_status s;
-    if ((s = hip_check(hipMalloc(&E.p, field * sizeof(double) * nl * p->grp_cs[0]), "kernel field")) != GF_OK)
+    if ((s = hip_check(dev_malloc((void **)&E.p, field * sizeof(double) * nl * p->grp_cs[0]), "kernel field")) != GF_OK)
         return s;
-    if ((s = hip_check(hipMalloc(&Rk.p, (size_t)p->M * p->py * 2 * sizeof(double) * nl * p->grp_cs[0]),
+    if ((s = hip_check(dev_malloc((void **)&Rk.p, (size_t)p->M * p->py * 2 * sizeof(double) * nl * p->grp_cs[0]),
                        "kernel row spectra")) != GF_OK)
         return s;
     const gf::KgenGeom g = kgen_geom(p);
@@ -340,11 +373,11 @@ void free_plan(gf_plan *p)
     for (int o = 0; o < 2; ++o)
         for (int i = 0; i < 4; ++i)
             if (p->ev[o][i]) (void)hipEventDestroy(p->ev[o][i]);
-    if (p->spec) (void)hipFree(p->spec);
-    if (p->tw) (void)hipFree(p->tw);
-    if (p->tw64 && p->tw64 != p->tw) (void)hipFree(p->tw64);
-    if (p->iws) (void)hipFree(p->iws);
-    if (p->zedge_dev) (void)hipFree(p->zedge_dev);
+    dev_free(p->spec);
+    dev_free(p->tw);
+    if (p->tw64 != p->tw) dev_free(p->tw64);
+    dev_free(p->iws);
+    dev_free(p->zedge_dev);
     delete p;
 }
 
@@ -366,6 +399,20 @@ const char *gf_status_string(gf_status s)
 }
 
 const char *gf_last_error(void) { return g_err.c_str(); }
+
+gf_status gf_debug_fail_alloc(int nth)
+{
+    if (nth < 0) return fail(GF_EINVAL, "nth must be >= 0");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_fail_countdown = nth;
+    return GF_OK;
+}
+
+size_t gf_debug_live_bytes(void)
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_live_bytes;
+}
 
 // Shared by the constructors: nt observation levels; `edges` holds the
 // nz + nt layer-edge depths of the nz + nt - 1 spectral layers, already
@@ -474,7 +521,7 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     }
 
     gf_status s;
-    if ((s = hip_check(hipMalloc(&p->zedge_dev, (p->nzs + 1) * sizeof(double)), "layer edges")) != GF_OK ||
+    if ((s = hip_check(dev_malloc((void **)&p->zedge_dev, (p->nzs + 1) * sizeof(double)), "layer edges")) != GF_OK ||
         (s = hip_check(hipMemcpy(p->zedge_dev, p->zedge.data(), (p->nzs + 1) * sizeof(double), hipMemcpyHostToDevice),
                        "layer edges")) != GF_OK) {
         free_plan(p);
@@ -483,7 +530,7 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     const int tl = 1 << p->twlog;
     {
         auto t64 = twiddle_table<double>(tl);
-        if ((s = hip_check(hipMalloc(&p->tw64, t64.size() * sizeof(double)), "twiddles")) != GF_OK) {
+        if ((s = hip_check(dev_malloc((void **)&p->tw64, t64.size() * sizeof(double)), "twiddles")) != GF_OK) {
             free_plan(p);
             return s;
         }
@@ -496,7 +543,7 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
             p->tw = p->tw64;
         } else {
             auto t32 = twiddle_table<float>(tl);
-            if ((s = hip_check(hipMalloc(&p->tw, t32.size() * sizeof(float)), "twiddles")) != GF_OK ||
+            if ((s = hip_check(dev_malloc((void **)&p->tw, t32.size() * sizeof(float)), "twiddles")) != GF_OK ||
                 (s = hip_check(hipMemcpy(p->tw, t32.data(), t32.size() * sizeof(float), hipMemcpyHostToDevice),
                                "twiddles")) != GF_OK) {
                 free_plan(p);
@@ -511,7 +558,7 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
                         p->grp_cs[g]);
         }
     p->spec_bytes = (size_t)p->nzs * p->U * p->n_spec * p->QP * p->elem();
-    if ((s = hip_check(hipMalloc(&p->spec, p->spec_bytes), "spectra")) != GF_OK) {
+    if ((s = hip_check(dev_malloc((void **)&p->spec, p->spec_bytes), "spectra")) != GF_OK) {
         free_plan(p);
         return s;
     }
@@ -521,7 +568,7 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     }
     if (max_batch > 0) {
         p->iws_bytes = std::max(p->ws_bytes(GF_OP_FORWARD, max_batch), p->ws_bytes(GF_OP_ADJOINT, max_batch));
-        if ((s = hip_check(hipMalloc(&p->iws, p->iws_bytes), "internal workspace")) != GF_OK) {
+        if ((s = hip_check(dev_malloc((void **)&p->iws, p->iws_bytes), "internal workspace")) != GF_OK) {
             free_plan(p);
             return s;
         }
@@ -846,7 +893,7 @@ gf_status gf_debug_kernel_table(const gf_plan *p, int n, double *host_out)
     const size_t field = (size_t)p->py * p->px;
     DevBuf E;
     gf_status s;
-    if ((s = hip_check(hipMalloc(&E.p, field * 8 * sizeof(double)), "debug field")) != GF_OK) return s;
+    if ((s = hip_check(dev_malloc((void **)&E.p, field * 8 * sizeof(double)), "debug field")) != GF_OK) return s;
     if ((s = hip_check(hipMemset(E.p, 0, field * 8 * sizeof(double)), "memset")) != GF_OK) return s;
     const int codes[8] = {0, 1, 2, 3, 4, 5, 7, 8};
     if (gf::launch_kgen_field(E.p, 1, n, 6, codes, kgen_geom(p), make_rules(), nullptr) != 0 ||

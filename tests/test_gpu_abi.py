@@ -132,3 +132,102 @@ def test_column_pass_groups(gf, ny, prec, mask, groups):
     p = gf.plan(4, ny, 1, 20.0, 20.0, 20.0, 10.0, mask, prec)
     assert p.col_groups == groups
     p.close()
+
+
+@pytest.mark.parametrize("kind,prec,max_batch", [("uniform", 0, 2), ("uniform", 1, 0), ("layered", 1, 1),
+                                                 ("levels", 0, 1)])
+def test_allocation_failure_returns_enomem_and_leaks_nothing(gf, kind, prec, max_batch):
+    """Every device allocation a plan makes (layer edges, twiddles, spectra,
+    plan-time scratch, the internal workspace) is made to fail in turn: plan
+    creation returns GF_ENOMEM with no plan, and the device memory the
+    library holds is back where it was.  The first allocation count that no
+    longer fails builds a plan whose forward matches one built normally."""
+    from paper_2005_10160_amd import _native
+    lib = _native.load()
+    g = Geometry(24, 40, 5, 20.0, 25.0, 15.0, 7.0)
+    zed = (ctypes.c_double * 6)(*[0.0, 4.0, 9.0, 15.0, 23.0, 33.0])
+    sh = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+    def create():
+        h = ctypes.c_void_p(12345)
+        if kind == "uniform":
+            rc = lib.gf_plan_create(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ctypes.c_uint(0x1FF), prec, max_batch,
+                                    sh, ctypes.byref(h))
+        elif kind == "layered":
+            rc = lib.gf_plan_create_layered(g.nx, g.ny, g.nz, g.dx, g.dy, zed, g.h, ctypes.c_uint(0x3F), prec,
+                                            max_batch, sh, ctypes.byref(h))
+        else:
+            rc = lib.gf_plan_create_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 3, ctypes.c_uint(0x3F), prec,
+                                           max_batch, sh, ctypes.byref(h))
+        return rc, h
+
+    base = lib.gf_debug_live_bytes()
+    failed = 0
+    try:
+        for nth in range(1, 20):
+            assert lib.gf_debug_fail_alloc(nth) == _native.GF_OK
+            rc, h = create()
+            if rc == _native.GF_OK:
+                break
+            assert rc == _native.GF_ENOMEM, (nth, _native.status_name(rc), lib.gf_last_error())
+            assert not h.value, nth
+            assert lib.gf_debug_live_bytes() == base, nth
+            failed += 1
+        else:
+            pytest.fail("plan creation never succeeded")
+    finally:
+        lib.gf_debug_fail_alloc(0)
+    assert failed >= 4 + (max_batch > 0) + (prec == 1)
+    try:
+        assert lib.gf_debug_live_bytes() > base
+        dt = torch.float64 if prec == 0 else torch.float32
+        rho = torch.from_numpy(tiny_density(g.nx, g.ny, g.nz, seed=75, block=None)).to("cuda", dt).unsqueeze(0)
+        info = _native.PlanInfo()
+        assert lib.gf_plan_get_info(h, ctypes.byref(info)) == _native.GF_OK
+        nt = info.n_levels
+        d = torch.empty((1, nt, info.n_out, g.ny, g.nx), dtype=dt, device="cuda")
+        need = ctypes.c_size_t()
+        assert lib.gf_workspace_bytes(h, 0, 1, ctypes.byref(need)) == _native.GF_OK
+        ws = torch.empty(need.value, dtype=torch.uint8, device="cuda")
+        assert lib.gf_forward(h, vp(rho), vp(d), 1, vp(ws), need.value, sh) == _native.GF_OK
+        ps = "f64" if prec == 0 else "f32"
+        if kind == "uniform":
+            p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x1FF, ps)
+        elif kind == "layered":
+            p = gf.plan_layered(g.nx, g.ny, g.dx, g.dy, list(zed), g.h, 0x3F, ps)
+        else:
+            p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 3, 0x3F, ps)
+        want = p.forward(rho)
+        torch.cuda.synchronize()
+        assert torch.equal(d.reshape(want.shape), want)
+        p.close()
+    finally:
+        lib.gf_plan_destroy(h)
+    assert lib.gf_debug_live_bytes() == base
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_nan_density_propagates(gf, prec):
+    """A NaN in one cell of the density is not an error: the call returns
+    normally and, since every cell reaches every station, every output is
+    NaN; the adjoint does the same with a NaN in the residual.  A model
+    without the NaN in the same batch is unaffected."""
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = Geometry(48, 40, 6, 20.0, 25.0, 15.0, 7.0)
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x1FF, prec)
+    rho = torch.from_numpy(np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (76, 77)]))
+    rho = rho.to("cuda", dt)
+    clean = p.forward(rho[1:])
+    rho[0, 3, 17, 29] = float("nan")
+    d = p.forward(rho)
+    torch.cuda.synchronize()
+    assert torch.isnan(d[0]).all()
+    assert torch.equal(d[1:], clean)
+    r = torch.randn(d.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(78)).to("cuda", dt)
+    clean_g = p.adjoint(r[1:])
+    r[0, 4, 10, 11] = float("nan")
+    gg = p.adjoint(r)
+    torch.cuda.synchronize()
+    assert torch.isnan(gg[0]).all()
+    assert torch.equal(gg[1:], clean_g)
+    p.close()
