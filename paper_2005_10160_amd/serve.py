@@ -15,9 +15,12 @@ virtual clock in tests:
     the group of the oldest pending request, in arrival order, up to
     ``max_models`` models;
   * a group is admitted when a stream slot is free and its bytes (workspace,
-    inputs and outputs, plus the spectra if they are not resident) fit in
-    the memory budget; idle cached spectra are evicted, least recently used
-    first, to make room;
+    inputs and outputs) fit in the memory budget; idle cached spectra are
+    evicted, least recently used first, to make room;
+  * a group whose spectra are not resident first reserves their bytes and
+    has them built in the background (``prepare``); it takes no slot and
+    holds nobody up while they are built, and is admitted like any other
+    once they are ready;
   * younger groups may pass an older one that does not fit yet, until the
     older one has waited ``backfill_limit`` seconds: then admission stops
     until memory drains for it;
@@ -32,11 +35,14 @@ scheduler in real time, and ``bench_served`` replays a seeded Poisson trace.
 """
 
 import collections
+import math
 import itertools
 import threading
 import time
 from dataclasses import dataclass, field
 from typing import Any, Optional, Tuple
+
+import numpy as np
 
 @dataclass(frozen=True)
 class GeometryKey:
@@ -81,6 +87,7 @@ class Request:
     error: Optional[str] = None
     t_admit: Optional[float] = None
     t_done: Optional[float] = None
+    cache: Optional[str] = None   # "hit": spectra resident on arrival; "miss": they had to be built
     keep_result: bool = True      # False: the output buffer is recycled once done (load replay)
     event: threading.Event = field(default_factory=threading.Event, repr=False)
 
@@ -117,8 +124,10 @@ def io_bytes(key: GeometryKey, op: str, batch: int, elem: int) -> int:
 class Scheduler:
     """Admission and batching policy.  ``executor`` must provide
     ``elem`` (bytes per value), ``workspace_bytes(key, op, batch)``,
-    ``is_resident(key)``, ``evict(key)``, ``launch(slot, requests)`` and
-    ``poll(slot) -> bool`` (True when the slot's launch has completed)."""
+    ``prepare(key)`` (start building the key's spectra without waiting),
+    ``ready(key) -> bool`` (True once built; raises if the build failed),
+    ``evict(key)``, ``launch(slot, requests)`` and ``poll(slot) -> bool``
+    (True when the slot's launch has completed)."""
 
     def __init__(self, executor, budget_bytes, n_slots=4, max_models=32, admit_timeout=30.0,
                  backfill_limit=0.25, clock=time.perf_counter):
@@ -132,7 +141,8 @@ class Scheduler:
         self.pending = collections.OrderedDict()      # (key, op) -> deque of requests
         self.slots = [None] * self.n_slots            # slot -> (requests, bytes, key)
         self.in_use = 0                               # bytes of running groups
-        self.resident = collections.OrderedDict()     # key -> bytes (LRU order)
+        self.resident = collections.OrderedDict()     # key -> bytes (LRU order), built or being built
+        self.building = set()                         # keys whose spectra are being built
         self.busy_keys = collections.Counter()        # key -> running groups using it
         self.completed = []
         self.stats = collections.Counter()
@@ -156,6 +166,7 @@ class Scheduler:
             self._finish(req, "rejected", "request needs %d bytes / %d models; budget %d bytes / %d models"
                          % (need, req.batch, self.budget, self.max_models))
             return False
+        req.cache = "hit" if req.key in self.resident and req.key not in self.building else "miss"
         self.pending.setdefault((req.key, req.op), collections.deque()).append(req)
         self.stats["submitted"] += 1
         return True
@@ -198,14 +209,50 @@ class Scheduler:
                 self._finish(q.popleft(), "rejected", "not admitted within %.3g s" % self.admit_timeout)
             if not q:
                 del self.pending[k]
+        for key in list(self.building):
+            try:
+                done = self.ex.ready(key)
+            except Exception as e:  # a failed build fails the key's requests, not the loop
+                self.building.discard(key)
+                self.resident.pop(key, None)
+                for k in [k for k in self.pending if k[0] == key]:
+                    for r in self.pending.pop(k):
+                        self._finish(r, "rejected", "spectra build failed: %s" % e)
+                continue
+            if done:
+                self.building.discard(key)
         launched = 0
         while self.pending and None in self.slots:
-            heads = sorted(self.pending.items(), key=lambda kv: kv[1][0].t_arrival)
+            # groups waiting for their spectra to be built are not in line
+            heads = sorted(((k, q) for k, q in self.pending.items() if k[0] not in self.building),
+                           key=lambda kv: kv[1][0].t_arrival)
+            if not heads:
+                break
             oldest_wait = now - heads[0][1][0].t_arrival
             chosen = None
             for i, ((key, op), q) in enumerate(heads):
                 if i > 0 and oldest_wait > self.backfill_limit:
                     break
+                if key not in self.resident:
+                    # reserve the spectra and have them built off this loop;
+                    # the group is admitted once they are ready
+                    need = spectra_bytes(key, self.ex.elem)
+                    if not self._make_room(need, key):
+                        continue
+                    self.resident[key] = need
+                    self.building.add(key)
+                    self.stats["spectra_miss"] += 1
+                    for k2, q2 in self.pending.items():
+                        if k2[0] == key:
+                            for r in q2:
+                                r.cache = "miss"
+                    self.ex.prepare(key)
+                    try:
+                        if not self.ex.ready(key):
+                            continue
+                    except Exception:
+                        continue                # reported at the next step
+                    self.building.discard(key)
                 group, models = [], 0
                 for r in q:
                     if models + r.batch > self.max_models:
@@ -213,13 +260,12 @@ class Scheduler:
                     group.append(r)
                     models += r.batch
                 nbytes = self.group_bytes(key, op, models)
-                miss = 0 if key in self.resident else spectra_bytes(key, self.ex.elem)
-                if self._make_room(nbytes + miss, key):
-                    chosen = (key, op, group, nbytes, miss)
+                if self._make_room(nbytes, key):
+                    chosen = (key, op, group, nbytes)
                     break
             if chosen is None:
                 break
-            key, op, group, nbytes, miss = chosen
+            key, op, group, nbytes = chosen
             q = self.pending[(key, op)]
             for r in group:
                 q.popleft()
@@ -227,11 +273,7 @@ class Scheduler:
                 r.t_admit = now
             if not q:
                 del self.pending[(key, op)]
-            if miss:
-                self.resident[key] = miss
-                self.stats["spectra_miss"] += 1
-            else:
-                self.stats["spectra_hit"] += 1
+            self.stats["spectra_hit" if all(r.cache == "hit" for r in group) else "launch_after_build"] += 1
             self.resident.move_to_end(key)
             slot = self.slots.index(None)
             self.slots[slot] = (group, nbytes, key)
@@ -247,6 +289,11 @@ class Scheduler:
                 self.busy_keys[key] -= 1
                 for r in group:
                     self._finish(r, "rejected", "launch failed: %s" % e)
+                # the key's spectra are not trusted after a failure: they are
+                # dropped and built again for the next request
+                if self.busy_keys[key] == 0 and key in self.resident:
+                    del self.resident[key]
+                    self.ex.evict(key)
                 continue
             launched += 1
         return launched
@@ -257,7 +304,7 @@ class Scheduler:
         for k in list(self.resident):
             if need <= self.free_bytes():
                 break
-            if k == key or self.busy_keys[k] > 0:
+            if k == key or self.busy_keys[k] > 0 or k in self.building:
                 continue
             del self.resident[k]
             self.ex.evict(k)
@@ -275,8 +322,9 @@ class GpuExecutor:
     """Launches a group on one of ``n_slots`` HIP streams: host inputs are
     copied into one batched device tensor, the operator runs once for the
     whole group, and each request's slice is copied back to its host
-    buffer.  Plans (resident spectra) are built on a miss on their own
-    stream."""
+    buffer.  Plans (resident spectra) are built on a worker thread, one at
+    a time, on a stream of their own (``prepare``/``ready``), so that the
+    scheduler keeps retiring and launching other groups meanwhile."""
 
     def __init__(self, precision="f32", n_slots=4, device="cuda:0"):
         import torch
@@ -291,6 +339,13 @@ class GpuExecutor:
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_slots)]
         self.plan_stream = torch.cuda.Stream(device=self.device)
         self.plans = {}
+        self.build_errors = {}
+        self.build_queue = collections.deque()
+        self.build_cv = threading.Condition()
+        self.building = None
+        self.builder_running = True
+        self.builder = threading.Thread(target=self._build_loop, daemon=True)
+        self.builder.start()
         self.events = [None] * n_slots
         self.keep = [None] * n_slots
         self.lock = threading.Lock()
@@ -298,26 +353,86 @@ class GpuExecutor:
         # by shape, for reuse
         self.out_pool = collections.defaultdict(list)
 
+    def _build_loop(self):
+        self.torch.cuda.set_device(self.device)
+        while True:
+            with self.build_cv:
+                while not self.build_queue and self.builder_running:
+                    self.build_cv.wait()
+                if not self.build_queue:
+                    return
+                key = self.build_queue.popleft()
+                if isinstance(key, GeometryKey):
+                    self.building = key
+            if not isinstance(key, GeometryKey):
+                key[1].close()              # ("close", plan) from evict
+                continue
+            try:
+                p = self._make_plan(key)
+                err = None
+            except Exception as e:
+                p, err = None, e
+            with self.build_cv:
+                if err is None:
+                    self.plans[key] = p
+                else:
+                    self.build_errors[key] = err
+                self.building = None
+                self.build_cv.notify_all()
+
+    def prepare(self, key):
+        """Start building the key's plan on the worker thread (no wait)."""
+        with self.build_cv:
+            if key in self.plans or key == self.building or key in self._queued_keys():
+                return
+            self.build_errors.pop(key, None)
+            self.build_queue.append(key)
+            self.build_cv.notify_all()
+
+    def _queued_keys(self):
+        return [k for k in self.build_queue if isinstance(k, GeometryKey)]
+
+    def ready(self, key):
+        """True once the key's plan is built; raises the build's error."""
+        with self.build_cv:
+            if key in self.build_errors:
+                raise self.build_errors[key]
+            return key in self.plans
+
+    def _make_plan(self, key):
+        if key.levels > 1:
+            return self.op_mod.plan_levels(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.levels,
+                                           key.components, self.precision, device=self.device,
+                                           stream=self.plan_stream)
+        if key.zedges is None:
+            return self.op_mod.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components,
+                                    self.precision, device=self.device, stream=self.plan_stream)
+        return self.op_mod.plan_layered(key.nx, key.ny, key.dx, key.dy, key.zedges, key.h, key.components,
+                                        self.precision, device=self.device, stream=self.plan_stream)
+
     def plan_for(self, key):
-        p = self.plans.get(key)
-        if p is None:
-            if key.levels > 1:
-                p = self.op_mod.plan_levels(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.levels,
-                                            key.components, self.precision, device=self.device,
-                                            stream=self.plan_stream)
-            elif key.zedges is None:
-                p = self.op_mod.plan(key.nx, key.ny, key.nz, key.dx, key.dy, key.dz, key.h, key.components,
-                                     self.precision, device=self.device, stream=self.plan_stream)
-            else:
-                p = self.op_mod.plan_layered(key.nx, key.ny, key.dx, key.dy, key.zedges, key.h, key.components,
-                                             self.precision, device=self.device, stream=self.plan_stream)
+        """The key's plan, waiting for (or making) it if it is not built."""
+        with self.build_cv:
+            p = self.plans.get(key)
+            if p is not None:
+                return p
+            queued = key == self.building or key in self._queued_keys()
+        if queued:
+            with self.build_cv:
+                while key not in self.plans and key not in self.build_errors:
+                    self.build_cv.wait()
+            self.ready(key)              # raises the build's error
+            return self.plans[key]
+        p = self._make_plan(key)
+        with self.build_cv:
             self.plans[key] = p
         return p
 
     def workspace_bytes(self, key, op, batch):
         # the plan's own figure when it exists; otherwise an upper bound of the
         # same layout (complex intermediates of the model and data sizes)
-        p = self.plans.get(key)
+        with self.build_cv:
+            p = self.plans.get(key)
         if p is not None:
             return p.workspace_bytes(op, batch)
         # forward: row-transformed model, up to 32 layer splits of partial
@@ -337,13 +452,20 @@ class GpuExecutor:
         return max(fwd, adj)
 
     def is_resident(self, key):
-        return key in self.plans
+        with self.build_cv:
+            return key in self.plans
 
     def evict(self, key):
-        p = self.plans.pop(key, None)
+        with self.build_cv:
+            p = self.plans.pop(key, None)
+            self.build_errors.pop(key, None)
         if p is not None:
-            self.plan_stream.synchronize()
-            p.close()
+            # the scheduler evicts only keys with no running group, so the
+            # plan's launches are done; it is freed on the worker thread
+            # (freeing device memory waits for the device)
+            with self.build_cv:
+                self.build_queue.append(("close", p))
+                self.build_cv.notify_all()
 
     def launch(self, slot, reqs):
         torch = self.torch
@@ -397,6 +519,11 @@ class GpuExecutor:
         return False
 
     def close(self):
+        with self.build_cv:
+            self.builder_running = False
+            self.build_queue = collections.deque(k for k in self.build_queue if not isinstance(k, GeometryKey))
+            self.build_cv.notify_all()
+        self.builder.join()
         self.torch.cuda.synchronize(self.device)
         for p in self.plans.values():
             p.close()
@@ -454,39 +581,82 @@ class Server:
 
 
 def _percentiles(vals):
-    import numpy as np
     if not vals:
         return None, None
     a = np.asarray(vals)
     return float(np.percentile(a, 50)), float(np.percentile(a, 99))
 
 
-def make_inputs(trace, precision, device="cuda:0"):
-    """Pinned host inputs for a trace: one buffer of the trace's largest batch
-    per (grid, operation) is drawn once (seeded); each request takes the
-    leading models of it."""
-    import torch
-    dt = torch.float32 if precision == "f32" else torch.float64
-    bmax = max(tr.batch for tr in trace)
-    pool = {}
-    gen = torch.Generator().manual_seed(500)
-    out = []
-    for tr in trace:
-        C = 6 if tr.full_tensor else 1
-        shape = (bmax, tr.nz, tr.n, tr.n) if tr.op == "forward" else (bmax, C, tr.n, tr.n)
-        k = (shape, tr.op)
-        if k not in pool:
-            t = torch.empty(shape, dtype=dt, pin_memory=True)
-            t.copy_(torch.rand(shape, generator=gen, dtype=torch.float64).sub_(0.5).mul_(1000.0))
-            pool[k] = t
-        out.append(pool[k][:tr.batch])
+def latency_summary(records):
+    """p50 / p99 latency (ms) of completed requests, overall and split by
+    whether their spectra were resident on arrival (hit) or had to be built
+    (miss)."""
+    out = {}
+    for name, sel in (("all", lambda r: True), ("hit", lambda r: r["cache"] == "hit"),
+                      ("miss", lambda r: r["cache"] == "miss")):
+        lat = [r["latency_ms"] for r in records if r["status"] == "done" and sel(r)]
+        p50, p99 = _percentiles(lat)
+        out[name] = {"n": len(lat), "p50_ms": p50, "p99_ms": p99}
     return out
+
+
+def request_shape(tr):
+    """Host input of a trace request: [B][nz][n][n] densities for a forward,
+    [B][C][n][n] residuals for an adjoint."""
+    C = 6 if tr.full_tensor else 1
+    return (tr.batch, tr.nz, tr.n, tr.n) if tr.op == "forward" else (tr.batch, C, tr.n, tr.n)
+
+
+class InputBank:
+    """Seeded host inputs for a request trace within a bounded buffer.
+
+    One flat buffer of uniform(-500, 500) values (seed 500) is drawn once,
+    its length the trace's largest request plus ``slack`` values; request r
+    takes the window starting at an offset drawn from a generator seeded by
+    the request's own seed, so every request carries its own models (the
+    same ones on every replay) while the pinned host memory stays bounded by
+    that one buffer."""
+
+    def __init__(self, trace, precision, pin=True, slack=1 << 24, seed=500):
+        import torch
+        dt = torch.float32 if precision == "f32" else torch.float64
+        self.largest = max(math.prod(request_shape(tr)) for tr in trace)
+        self.n = self.largest + int(slack)
+        self.buf = torch.empty(self.n, dtype=dt, pin_memory=pin)
+        gen = torch.Generator().manual_seed(seed)
+        chunk = 1 << 24
+        for o in range(0, self.n, chunk):
+            m = min(chunk, self.n - o)
+            self.buf[o:o + m].copy_(torch.rand(m, generator=gen, dtype=torch.float64).sub_(0.5).mul_(1000.0))
+
+    @property
+    def nbytes(self):
+        return self.buf.numel() * self.buf.element_size()
+
+    def offset(self, tr):
+        size = math.prod(request_shape(tr))
+        rng = np.random.default_rng(tr.seed)
+        return int(rng.integers(0, self.n - size + 1))
+
+    def get(self, tr):
+        shape = request_shape(tr)
+        o = self.offset(tr)
+        return self.buf[o:o + math.prod(shape)].view(shape)
+
+
+def make_inputs(trace, precision, pin=True):
+    """The inputs of every request of a trace, as views of one InputBank."""
+    bank = InputBank(trace, precision, pin=pin)
+    return [bank.get(tr) for tr in trace]
 
 
 def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=4, max_models=32,
            time_limit=None):
     """Replay arrivals in real time.  batched=False gives the plain baseline:
-    one stream, FIFO, one model per call."""
+    one stream, FIFO, one model per call.  Returns the summary and one record
+    per request: arrival, admission and completion times (seconds from the
+    start of the replay, admission of its first model for the baseline), its
+    latency, and whether its spectra were resident on arrival."""
     ex = executor_factory(n_slots if batched else 1)
     if batched:
         srv = Server(ex, budget_bytes, n_slots=n_slots, max_models=max_models, admit_timeout=None)
@@ -504,7 +674,7 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
         if batched:
             r = Request(tr.rid, key, tr.op, tr.batch, time.perf_counter(), x, keep_result=False)
             srv.submit(r)
-            reqs.append([r])
+            reqs.append((tr, [r]))
         else:
             # the plain operator: one model per call, in arrival order
             t_arr = time.perf_counter()
@@ -513,40 +683,83 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
                 r = Request(tr.rid * 100 + b, key, tr.op, 1, t_arr, x[b:b + 1], keep_result=False)
                 srv.submit(r)
                 parts.append(r)
-            reqs.append(parts)
-    for parts in reqs:
+            reqs.append((tr, parts))
+    for _, parts in reqs:
         for r in parts:
             r.wait()
     wall = time.perf_counter() - t0
     srv.close()
     stats = dict(srv.sched.stats)
     ex.close()
-    lat = []
+    records = []
     evals = 0.0
-    for parts in reqs:
-        if all(r.status == "done" for r in parts):
-            lat.append(max(r.t_done for r in parts) - parts[0].t_arrival)
+    for tr, parts in reqs:
+        done = all(r.status == "done" for r in parts)
+        t_done = max(r.t_done for r in parts) if done else None
+        admits = [r.t_admit for r in parts if r.t_admit is not None]
+        records.append({
+            "rid": tr.rid, "n": tr.n, "nz": tr.nz, "batch": tr.batch, "op": tr.op,
+            "components": 6 if tr.full_tensor else 1,
+            "status": "done" if done else parts[0].status,
+            "cache": "hit" if all(r.cache == "hit" for r in parts) else "miss",
+            "t_arrival": parts[0].t_arrival - t0,
+            "t_admit": (min(admits) - t0) if admits else None,
+            "t_done": (t_done - t0) if done else None,
+            "latency_ms": (t_done - parts[0].t_arrival) * 1e3 if done else None,
+        })
+        if done:
             k = parts[0].key
-            evals += sum(r.batch for r in parts) * k.n_out * (k.nx * k.ny) ** 2 * k.nz
-    p50, p99 = _percentiles(lat)
-    return {"requests": len(reqs), "completed": len(lat), "wall_s": wall,
-            "p50_ms": None if p50 is None else p50 * 1e3, "p99_ms": None if p99 is None else p99 * 1e3,
-            "requests_per_s": len(lat) / wall, "effective_evals_per_s": evals / wall, "stats": stats}
+            evals += tr.batch * k.n_out * (k.nx * k.ny) ** 2 * k.nz
+    lat = latency_summary(records)
+    completed = lat["all"]["n"]
+    return {"requests": len(reqs), "completed": completed, "wall_s": wall,
+            "p50_ms": lat["all"]["p50_ms"], "p99_ms": lat["all"]["p99_ms"],
+            "hit": lat["hit"], "miss": lat["miss"],
+            "requests_per_s": completed / wall, "effective_evals_per_s": evals / wall, "stats": stats,
+            "records": records}
 
 
-def bench_served(seconds=3.0, rate=200.0, budget_gb=64.0):
-    """Seeded Poisson trace (rate req/s) of mixed grids, replayed through the
-    FP32 continuous-batching server and through the plain FP64 operator
-    (FIFO, one model per call), both with the spectra cache on."""
+def bench_served(seconds=20.0, rate=200.0, budget_gb=64.0, baseline_seconds=3.0, records_path=None):
+    """Seeded Poisson trace (rate req/s, `seconds` long: 4000 requests by
+    default) of mixed grids, replayed through the FP32 continuous-batching
+    server; the plain FP64 operator (FIFO, one model per call) replays the
+    first `baseline_seconds` of the same trace (it falls behind the arrival
+    rate, so a longer replay only grows its queue), and the served figures
+    over that same prefix are reported beside it.  Both keep the spectra
+    cache.  The per-request records go to `records_path` (CSV) when given;
+    the summary names the ten slowest served requests."""
     from synth import poisson_trace
     n = max(1, int(seconds * rate))
     trace = poisson_trace(n_requests=n, rate=rate, seed=500)
     budget = int(budget_gb * (1 << 30))
     out = {"trace": "poisson %.0f req/s, %d requests (%.1f s), seed 500" % (rate, n, trace[-1].t_arrival)}
-    in32 = make_inputs(trace, "f32")
-    out["served_f32"] = replay(trace, in32, lambda k: GpuExecutor("f32", k), budget, batched=True)
-    del in32
-    in64 = make_inputs(trace, "f64")
-    out["plain_f64"] = replay(trace, in64, lambda k: GpuExecutor("f64", k), budget, batched=False,
-                              time_limit=4 * seconds)
+    bank = InputBank(trace, "f32")
+    out["input_bank_bytes"] = bank.nbytes
+    served = replay(trace, [bank.get(tr) for tr in trace], lambda k: GpuExecutor("f32", k), budget, batched=True)
+    del bank
+    recs = served.pop("records")
+    nb = max(1, int(baseline_seconds * rate))
+    served["first_%d" % nb] = latency_summary(recs[:nb])
+    served["slowest"] = sorted((r for r in recs if r["latency_ms"] is not None),
+                               key=lambda r: -r["latency_ms"])[:10]
+    out["served_f32"] = served
+    if records_path:
+        import csv
+        with open(records_path, "w", newline="") as fh:
+            w = csv.DictWriter(fh, fieldnames=list(recs[0].keys()))
+            w.writeheader()
+            w.writerows(recs)
+    # the served run's pinned buffer goes back to the system before the
+    # baseline's (torch keeps freed pinned blocks cached otherwise)
+    import gc
+    import torch
+    gc.collect()
+    if hasattr(torch._C, "_host_emptyCache"):
+        torch._C._host_emptyCache()
+    sub = trace[:nb]
+    bank = InputBank(sub, "f64")
+    plain = replay(sub, [bank.get(tr) for tr in sub], lambda k: GpuExecutor("f64", k), budget, batched=False)
+    del bank
+    plain.pop("records")
+    out["plain_f64"] = plain
     return out

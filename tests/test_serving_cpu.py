@@ -20,12 +20,22 @@ class FakeExecutor:
 
     elem = 4
 
-    def __init__(self, clock, cost=lambda k, op, b: 0.010):
+    def __init__(self, clock, cost=lambda k, op, b: 0.010, build=0.0):
         self.clock = clock
         self.cost = cost
+        self.build = build            # virtual seconds to build a key's spectra
         self.busy = {}
         self.launched = []
         self.evicted = []
+        self.built = {}               # key -> virtual time its spectra are ready
+        self.prepared = []
+
+    def prepare(self, key):
+        self.prepared.append(key)
+        self.built[key] = self.clock() + self.build
+
+    def ready(self, key):
+        return self.clock() >= self.built[key]
 
     def workspace_bytes(self, key, op, batch):
         return 1000 * batch
@@ -35,6 +45,7 @@ class FakeExecutor:
 
     def evict(self, key):
         self.evicted.append(key)
+        self.built.pop(key, None)
 
     def launch(self, slot, reqs):
         models = sum(r.batch for r in reqs)
@@ -231,3 +242,138 @@ def test_level_and_layered_keys():
     lay = GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x1, (0.0, 1.0, 3.0))
     assert lay != GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x1, (0.0, 1.0, 4.0))
     assert lay != GeometryKey(16, 16, 2, 1.0, 1.0, 1.0, 1.0, 0x1)
+
+
+def test_hit_is_admitted_while_a_miss_builds_its_spectra():
+    """A request whose spectra are not resident starts their build and waits
+    for it off the scheduling loop: a later request of a resident geometry
+    is admitted and finishes meanwhile, and the first is admitted as soon
+    as its spectra are ready.  Each request records whether it was a hit."""
+    clock = Clock()
+    ex = FakeExecutor(clock, cost=lambda k, op, b: 0.010, build=0.5)
+    s = Scheduler(ex, budget_bytes=1 << 40, n_slots=2, clock=clock)
+    warm = key(64)
+    s.submit(req(0, warm, 0.0))
+    run_until_idle(s, clock)                 # warm's spectra are now resident
+    t1 = clock.t
+    cold = req(1, key(256), t1)
+    s.submit(cold)
+    s.step()
+    assert ex.prepared[-1] == key(256) and cold.status == "pending"
+    clock.t = t1 + 0.05
+    hit = req(2, warm, clock.t)
+    s.submit(hit)
+    s.step()
+    assert hit.status == "running" and cold.status == "pending"
+    clock.t = t1 + 0.1
+    s.step()
+    assert hit.status == "done" and cold.status == "pending"
+    clock.t = t1 + 0.51
+    s.step()
+    assert cold.status == "running" and cold.t_admit == pytest.approx(t1 + 0.51)
+    run_until_idle(s, clock)
+    assert cold.status == "done"
+    assert (cold.cache, hit.cache) == ("miss", "hit")
+    assert s.stats["spectra_miss"] == 2 and s.stats["spectra_hit"] == 1 and s.stats["launch_after_build"] == 2
+
+
+def test_requests_arriving_during_a_build_are_misses_and_batched():
+    """Requests of a geometry whose spectra are being built wait for that one
+    build (no second build starts) and are then launched together."""
+    clock = Clock()
+    ex = FakeExecutor(clock, build=0.3)
+    s = Scheduler(ex, budget_bytes=1 << 40, n_slots=1, max_models=8, clock=clock)
+    k = key(128)
+    a = req(0, k, 0.0)
+    s.submit(a)
+    s.step()
+    clock.t = 0.1
+    b = req(1, k, 0.1)
+    s.submit(b)
+    s.step()
+    assert ex.prepared == [k] and a.status == b.status == "pending"
+    clock.t = 0.31
+    s.step()
+    assert ex.launched[-1][1] == [0, 1]
+    assert a.cache == b.cache == "miss"
+
+
+def test_failed_build_rejects_that_geometry_only():
+    clock = Clock()
+
+    class BadBuild(FakeExecutor):
+        def ready(self, key):
+            if key.nx == 128:
+                raise RuntimeError("no memory for spectra")
+            return super().ready(key)
+
+    ex = BadBuild(clock)
+    s = Scheduler(ex, budget_bytes=1 << 40, n_slots=2, clock=clock)
+    bad, good = req(0, key(128), 0.0), req(1, key(64), 0.0)
+    s.submit(bad)
+    s.submit(good)
+    run_until_idle(s, clock)
+    assert bad.status == "rejected" and "spectra build failed" in bad.error
+    assert good.status == "done"
+    assert key(128) not in s.resident and not s.building
+
+
+def test_failed_launch_drops_the_resident_spectra():
+    """After a launch fails, its geometry's spectra are not counted as
+    resident: the next request of that geometry is a miss and rebuilds."""
+    clock = Clock()
+
+    class FailOnce(FakeExecutor):
+        failed = False
+
+        def launch(self, slot, reqs):
+            if not self.failed:
+                self.failed = True
+                raise RuntimeError("boom")
+            super().launch(slot, reqs)
+
+    ex = FailOnce(clock)
+    s = Scheduler(ex, budget_bytes=1 << 40, n_slots=1, clock=clock)
+    k = key(64)
+    first = req(0, k, 0.0)
+    s.submit(first)
+    run_until_idle(s, clock)
+    assert first.status == "rejected" and k not in s.resident and ex.evicted == [k]
+    second = req(1, k, clock.t)
+    s.submit(second)
+    assert second.cache == "miss"
+    run_until_idle(s, clock)
+    assert second.status == "done" and ex.prepared == [k, k]
+
+
+def test_input_bank_is_bounded_and_seeded_per_request():
+    """The served replay's host inputs: one buffer of the largest request
+    plus a fixed slack, whatever the trace's length; each request's window
+    depends on its own seed only, so requests differ from one another and a
+    request is the same on every replay."""
+    import numpy as np
+    from paper_2005_10160_amd.serve import InputBank, request_shape
+    from synth import poisson_trace
+    trace = poisson_trace(n_requests=300, rate=200.0, seed=500, n_choices=(16, 32), nz_choices=(4, 8))
+    bank = InputBank(trace, "f32", pin=False, slack=1 << 16)
+    largest = max(int(np.prod(request_shape(tr))) for tr in trace)
+    assert bank.nbytes == 4 * (largest + (1 << 16))
+    again = InputBank(trace[:50], "f32", pin=False, slack=1 << 16)
+    for tr in trace[:50]:
+        x = bank.get(tr)
+        assert tuple(x.shape) == request_shape(tr)
+        assert float(x.abs().max()) <= 500.0
+        if again.largest == bank.largest:
+            assert bool((again.get(tr) == x).all())
+    offsets = [bank.offset(tr) for tr in trace]
+    assert len(set(offsets)) > 0.95 * len(offsets)
+
+
+def test_latency_summary_splits_hits_and_misses():
+    from paper_2005_10160_amd.serve import latency_summary
+    recs = [{"status": "done", "cache": "hit", "latency_ms": float(v)} for v in range(1, 101)]
+    recs += [{"status": "done", "cache": "miss", "latency_ms": 1000.0 + v} for v in range(10)]
+    recs += [{"status": "rejected", "cache": "miss", "latency_ms": None}]
+    s = latency_summary(recs)
+    assert (s["all"]["n"], s["hit"]["n"], s["miss"]["n"]) == (110, 100, 10)
+    assert s["hit"]["p50_ms"] == pytest.approx(50.5) and s["miss"]["p50_ms"] == pytest.approx(1004.5)
