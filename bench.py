@@ -20,9 +20,12 @@ the equal-dimension survey (as many observation levels as layers),
 the batched inversion-step workload (512^2 x 128, 32 models, forward
 and adjoint in both precisions), the CPU oracle timed on a bounded sample,
 and a served-latency run:
-a seeded Poisson trace of mixed requests (3 s at 200 req/s by default)
-replayed through the FP32 continuous-batching server and through the plain
-FP64 operator (FIFO, one model per call), each with p50/p99 latency.
+a seeded Poisson trace of mixed requests (4000 at 200 req/s by default)
+replayed through the FP32 continuous-batching server (p50/p99 latency
+overall and apart for requests whose kernel spectra were resident on
+arrival and for those that waited for them to be built, and the ten
+slowest requests), and its first 3 s through the plain FP64 operator (FIFO,
+one model per call).
 """
 
 import argparse
@@ -333,8 +336,10 @@ def main():
     ap.add_argument("--no-sets", action="store_true", help="skip the gz/gx/gy and nine-component timings")
     ap.add_argument("--configs", action="store_true",
                     help="add the per-configuration table (tiny, medium, paper scale: apply times)")
-    ap.add_argument("--serve-seconds", type=float, default=3.0,
-                    help="length of the replayed request trace (0: no serving run)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the replayed request trace at 200 req/s (0: no serving run)")
+    ap.add_argument("--serve-records", default=None,
+                    help="write one CSV line per served request (arrival, admission, completion, cache hit)")
     ap.add_argument("--small", action="store_true", help="medium 256^2x64 grid (quick check)")
     ap.add_argument("--calibrate", action="store_true",
                     help="also run a plain 1 GiB elementwise copy (read 1 GiB, write 1 GiB) so that "
@@ -384,11 +389,14 @@ def main():
             for _ in range(warmup):
                 p.adjoint(d, g_out, ws)
             torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(steps):
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(steps)]
+            for a, e in ev:
+                a.record()
                 p.adjoint(d, g_out, ws)
+                e.record()
             torch.cuda.synchronize()
-            res["adjoint_ms"] = (time.perf_counter() - t0) * 1e3 / steps
+            res["adjoint_ms"] = statistics.median(a.elapsed_time(e) for a, e in ev)
             res["adjoint_passes"] = time_passes(p, g_out, d, ws, steps, "adjoint")
         return res
 
@@ -404,14 +412,20 @@ def main():
     evals = 6.0 * g.nd * g.nm
     main_res = run(args.precision, args.steps, args.warmup, not args.no_adjoint)
     per = main_res["per"]
-    total_ms = sum(per)
-    ms_per_step = total_ms / len(per)
+    # the apply time is the median of the timed applies
+    ms_per_step = statistics.median(per)
     value = evals / (ms_per_step * 1e-3)
 
     p = main_res["plan"]
-    alg_bytes, S = colpass_algorithmic_bytes(p, 1)
+    # compulsory bytes of one apply: resident spectra once, density in, data
+    # out (the intermediate spectra of the density are not counted)
+    s_el = 8 if args.precision == "f64" else 4
+    compulsory = (p.spectra_bytes + s_el * (g.nz * g.nx * g.ny + 6 * g.nx * g.ny))
+    model_bytes, S = colpass_algorithmic_bytes(p, 1)
+    # the dominant kernel's average launch duration, from HIP events the
+    # library records on the launch stream around the column pass
     col_ms = float(np.mean(main_res["passes"][:, 1]))
-    achieved = alg_bytes / (col_ms * 1e-3) / 1e9
+    achieved = compulsory / (col_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE) and not args.small:
         try:
@@ -423,17 +437,24 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": "col_forward_ws_kernel (FFT along y + layer reduction + inverse FFT)",
-                "algorithmic_bytes_per_launch": alg_bytes, "layer_splits": S,
-                "kernel_ms": round(col_ms, 4)}
-    # whole-apply compulsory bytes: resident spectra once, density in, data out
-    s_el = 8 if args.precision == "f64" else 4
-    compulsory = (p.spectra_bytes + s_el * (g.nz * g.nx * g.ny + 6 * g.nx * g.ny))
+                "kernel_ms": round(col_ms, 4),
+                "algorithmic_bytes_per_launch": int(compulsory),
+                "algorithmic_bytes": "compulsory bytes of one apply (resident spectra once, density in, "
+                                     "data out); one column-pass launch serves one apply",
+                # what the kernel itself must move (spectra, the row-transformed
+                # density and the partial data columns), and the counters' bytes
+                "kernel_model_bytes_per_launch": model_bytes,
+                "kernel_model_GBs": round(model_bytes / (col_ms * 1e-3) / 1e9, 1),
+                "kernel_model_frac": round(model_bytes / (col_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "traffic_frac": (None if traffic is None
+                                 else round(traffic / (col_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)),
+                "layer_splits": S}
     pct = np.percentile(per, [10, 50, 90])
     log("bench: device streaming rates")
     copy_gbs, read_gbs = stream_bandwidth(dev)
     roofline["practical_copy_GBs"] = round(copy_gbs, 1)
     roofline["practical_read_GBs"] = round(read_gbs, 1)
-    roofline["frac_of_read"] = round(achieved / read_gbs, 4)
+    roofline["kernel_model_frac_of_read"] = round(model_bytes / (col_ms * 1e-3) / 1e9 / read_gbs, 4)
     line = {
         "metric": METRIC,
         "value": value,
@@ -452,7 +473,7 @@ def main():
                    "nx": g.nx, "ny": g.ny, "nz": g.nz, "components": 6, "batch": 1,
                    "precision": args.precision},
         "roofline": roofline,
-        "median_ms": statistics.median(per),
+        "mean_ms": float(np.mean(per)),
         "p10_ms": float(pct[0]),
         "p90_ms": float(pct[2]),
         "apply_compulsory": {"bytes": int(compulsory),
@@ -479,12 +500,16 @@ def main():
 
     if not args.no_f32 and args.precision == "f64":
         r32 = run("f32", args.steps, args.warmup, False)
-        ms32 = sum(r32["per"]) / len(r32["per"])
+        ms32 = statistics.median(r32["per"])
         a32, _ = colpass_algorithmic_bytes(r32["plan"], 1)
         c32 = float(np.mean(r32["passes"][:, 1]))
+        comp32 = r32["spectra_bytes"] + 4 * (g.nz * g.nx * g.ny + 6 * g.nx * g.ny)
         line["f32"] = {"value": evals / (ms32 * 1e-3), "ms_per_step": ms32,
                        "pass_ms": [round(float(x), 4) for x in r32["passes"].mean(axis=0)],
-                       "colpass_GBs": round(a32 / (c32 * 1e-3) / 1e9, 1), "plan_ms": round(r32["plan_ms"], 1)}
+                       "roofline_frac": round(comp32 / (c32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "apply_compulsory_frac_of_8TBs": round(comp32 / (ms32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                       "kernel_model_GBs": round(a32 / (c32 * 1e-3) / 1e9, 1),
+                       "plan_ms": round(r32["plan_ms"], 1)}
         r32["plan"].close()
         del r32
 
@@ -500,7 +525,7 @@ def main():
             sets[name] = {}
             for prec in ("f64", "f32"):
                 r = run(prec, 10, 2, True, mask, ze)
-                ms = sum(r["per"]) / len(r["per"])
+                ms = statistics.median(r["per"])
                 nout = r["plan"].n_out
                 sets[name][prec] = {"components": nout, "ms_per_step": round(ms, 4),
                                     "effective_evals_per_s": nout * g.nd * g.nm / (ms * 1e-3),
@@ -523,7 +548,7 @@ def main():
             lev[name] = {}
             for prec in ("f64", "f32"):
                 r = run(prec, 3, 1, True, mask, None, g.nz)
-                ms = sum(r["per"]) / len(r["per"])
+                ms = statistics.median(r["per"])
                 evals_l = r["plan"].n_out * g.nz * g.nd * g.nm
                 lev[name][prec] = {"ms_per_step": round(ms, 3), "effective_evals_per_s": evals_l / (ms * 1e-3),
                                    "adjoint_ms": round(r["adjoint_ms"], 3), "plan_ms": round(r["plan_ms"], 1),
@@ -540,7 +565,7 @@ def main():
 
     if args.serve_seconds > 0:
         from paper_2005_10160_amd import serve
-        line["served"] = serve.bench_served(args.serve_seconds)
+        line["served"] = serve.bench_served(args.serve_seconds, records_path=args.serve_records)
 
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
