@@ -210,6 +210,23 @@ gf_status gf_forward(gf_plan *plan, const void *rho, void *d, int batch, void *w
 gf_status gf_adjoint(gf_plan *plan, const void *r, void *g, int batch, void *workspace,
                      size_t workspace_bytes, void *hip_stream);
 
+/*
+ * gf_forward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same operator and results as gf_forward, with the workspace taken
+ * from a fixed 128 MiB array of device memory that the library reserves on
+ * each device when its device code is loaded there (held until the process
+ * ends).  The call itself allocates nothing.
+ *   rho, d, batch, hip_stream  as gf_forward; the current device must be
+ *                              the plan's device (else GF_EINVAL)
+ * Returns GF_EBUSY when gf_workspace_bytes(FORWARD, batch) exceeds the
+ * 128 MiB.  Every call on one device shares that device's array and the
+ * workspace needs no clearing between calls; calls that overlap in time on
+ * one device (other streams, other threads) race on it, so callers must
+ * order them on one stream or otherwise serialise them.
+ */
+gf_status gf_forward_noalloc(gf_plan *plan, const void *rho, void *d, int batch, void *hip_stream);
+
 /* Per-pass timing, for benchmarks.  When enabled, gf_forward and gf_adjoint
  * record a HIP event before and after each of their three passes (row
  * transform, column pass with the layer reduction, inverse row transform) on

@@ -21,6 +21,7 @@ EXPORTED = (
     "gf_workspace_bytes", "gf_forward", "gf_adjoint", "gf_status_string",
     "gf_last_error", "gf_debug_kernel_table", "gf_debug_spectrum",
     "gf_plan_set_timing", "gf_plan_last_pass_ms", "gf_debug_fail_alloc", "gf_debug_live_bytes",
+    "gf_forward_noalloc",
 )
 
 
@@ -90,6 +91,8 @@ def load(path=None):
         lib.gf_plan_set_timing.restype = i
         lib.gf_plan_last_pass_ms.argtypes = [vp, i, pd]
         lib.gf_plan_last_pass_ms.restype = i
+        lib.gf_forward_noalloc.argtypes = [vp, vp, vp, i, vp]
+        lib.gf_forward_noalloc.restype = i
         lib.gf_debug_fail_alloc.argtypes = [i]
         lib.gf_debug_fail_alloc.restype = i
         lib.gf_debug_live_bytes.argtypes = []

@@ -383,6 +383,39 @@ void free_plan(gf_plan *p)
 
 }  // namespace
 
+// Workspace of gf_forward_noalloc: a fixed array in device memory, one per
+// device, reserved when the library's device code is loaded on it and held
+// until the process ends.  Host code never passes `scratch` itself to a
+// kernel (on the host it names a stand-in, not the device address); it uses
+// the device address looked up once per device below.
+constexpr size_t kScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up on the
+// first call on each device).
+gf_status scratch_address(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(GF_EUNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(GF_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return GF_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *gf_status_string(gf_status s)
@@ -759,6 +792,23 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
     }
     mark(p, GF_OP_FORWARD, 3, st);
     return GF_OK;
+}
+
+gf_status gf_forward_noalloc(gf_plan *p, const void *rho, void *d, int batch, void *hip_stream)
+{
+    if (!p || !rho || !d) return fail(GF_EINVAL, "NULL argument");
+    if (batch < 1) return fail(GF_EINVAL, "batch must be >= 1");
+    const size_t need = p->ws_bytes(GF_OP_FORWARD, batch);
+    if (need > kScratchBytes)
+        return fail(GF_EBUSY, "batch %d needs %zu bytes of workspace, beyond the %zu-byte fixed scratch", batch, need,
+                    kScratchBytes);
+    int dev = -1;
+    gf_status s = hip_check(hipGetDevice(&dev), "current device");
+    if (s != GF_OK) return s;
+    if (dev != p->device) return fail(GF_EINVAL, "current device %d is not the plan's device %d", dev, p->device);
+    void *ws = nullptr;
+    if ((s = scratch_address(dev, &ws)) != GF_OK) return s;
+    return gf_forward(p, rho, d, batch, ws, kScratchBytes, hip_stream);
 }
 
 gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *workspace,
