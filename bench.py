@@ -551,8 +551,11 @@ def main():
                 ms = statistics.median(r["per"])
                 evals_l = r["plan"].n_out * g.nz * g.nd * g.nm
                 lev[name][prec] = {"ms_per_step": round(ms, 3), "effective_evals_per_s": evals_l / (ms * 1e-3),
-                                   "adjoint_ms": round(r["adjoint_ms"], 3), "plan_ms": round(r["plan_ms"], 1),
-                                   "spectra_bytes": r["spectra_bytes"]}
+                                   "pass_ms": [round(float(x), 3) for x in r["passes"].mean(axis=0)],
+                                   "adjoint_ms": round(r["adjoint_ms"], 3),
+                                   "adjoint_pass_ms": [round(float(x), 3) for x in r["adjoint_passes"].mean(axis=0)],
+                                   "level_path": r["plan"].level_path, "level_chunk": r["plan"].level_chunk,
+                                   "plan_ms": round(r["plan_ms"], 1), "spectra_bytes": r["spectra_bytes"]}
                 r["plan"].close()
                 del r
         line["levels"] = lev

@@ -108,6 +108,12 @@ typedef struct {
                               or one where LDS holds fewer at this column
                               length), each group re-reading the row-
                               transformed density                             */
+    int level_path;        /* how the levels run: 0 one plane; 1 a column pass
+                              per level; 2 column passes of several levels;
+                              3 the Toeplitz product in depth (the column
+                              transforms once, the depth products of every
+                              level per frequency, the inverse transforms once) */
+    int level_chunk;       /* levels per chunk of path 3 (0 otherwise)           */
 } gf_plan_info_t;
 
 /*
@@ -261,6 +267,17 @@ gf_status gf_debug_kernel_table(const gf_plan *plan, int n, double *host_out);
  * gz, gxx, gxy, gyy, the imaginary part for gxz, gyz, gx, gy (unit
  * gravitational constant). */
 gf_status gf_debug_spectrum(const gf_plan *plan, unsigned component, int n, double *host_out);
+
+/*
+ * Test hook: how plans of several observation levels created afterwards run
+ * them.  mode 0: the path whose estimated traffic is lowest (the default);
+ * 1: column passes (one or several levels each); 2: the Toeplitz product in
+ * depth, where the transform length allows it (column lengths >= 256).
+ * max_chunk > 0 caps the levels per chunk of the Toeplitz path (0: its
+ * default, 32 GiB of chunk buffers per model).  Process-wide.  GF_EINVAL for
+ * other values.
+ */
+gf_status gf_debug_level_path(int mode, int max_chunk);
 
 /*
  * Failure injection, for tests of the error paths: the nth device

@@ -21,7 +21,7 @@ EXPORTED = (
     "gf_workspace_bytes", "gf_forward", "gf_adjoint", "gf_status_string",
     "gf_last_error", "gf_debug_kernel_table", "gf_debug_spectrum",
     "gf_plan_set_timing", "gf_plan_last_pass_ms", "gf_debug_fail_alloc", "gf_debug_live_bytes",
-    "gf_forward_noalloc",
+    "gf_forward_noalloc", "gf_debug_level_path",
 )
 
 
@@ -36,6 +36,8 @@ class PlanInfo(ctypes.Structure):
         ("plan_ms", ctypes.c_double),
         ("n_levels", ctypes.c_int),
         ("col_groups", ctypes.c_int),
+        ("level_path", ctypes.c_int),
+        ("level_chunk", ctypes.c_int),
     ]
 
 
@@ -91,6 +93,8 @@ def load(path=None):
         lib.gf_plan_set_timing.restype = i
         lib.gf_plan_last_pass_ms.argtypes = [vp, i, pd]
         lib.gf_plan_last_pass_ms.restype = i
+        lib.gf_debug_level_path.argtypes = [i, i]
+        lib.gf_debug_level_path.restype = i
         lib.gf_forward_noalloc.argtypes = [vp, vp, vp, i, vp]
         lib.gf_forward_noalloc.restype = i
         lib.gf_debug_fail_alloc.argtypes = [i]

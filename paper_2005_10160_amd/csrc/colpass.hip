@@ -1490,6 +1490,405 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     }
 }
 
+// ---------------------------------------------------------------------------
+// Observation levels as a Toeplitz product in depth (the equal-dimension
+// survey: eq. 10-11 and the block matrix after eq. 22).
+//
+// Level t of the forward operator is d^_{t,c}(k) = sum_n conj(K^_{c,n+t}(k))
+// rho^_n(k): at each frequency a Toeplitz product along depth.  Instead of a
+// column pass per level (each re-reading the density and nz spectral
+// layers), three steps run once each:
+//   col_spectra_ws_kernel   y-transform of every column into its spectrum
+//   levels_*_toeplitz_kernel the depth products of a block of levels at
+//                           each frequency, every spectral layer of the
+//                           block's window read once
+//   col_inverse_ws_kernel   inverse y-transform of every output spectrum
+// The adjoint runs the same steps with levels and layers exchanged:
+// g^_n(k) = sum_t sum_c K^_{c,n+t}(k) r^_{t,c}(k).
+//
+// A column's spectrum (ky in [0, N)) is stored as two rows of QP values in
+// the order of the resident spectrum rows: row 0 holds ky = q at spec_pos(q)
+// for q in [0, N/2), row 1 holds ky = N - q at spec_pos(q) for q in [1, N/2],
+// so that a component's resident quarter-plane row gives K^ for both rows
+// at the same position (with the component's y-parity sign on row 1).
+// Entries no frequency maps to are neither written nor read as data.  A
+// slab is [M+1 rows in spec_row order][2][QP] complex values.
+
+// Work of one group of the transform kernels: virtual unit uv of model b;
+// the block's groups share the slab range (blockIdx.y), so every group of a
+// block runs the same number of workgroup barriers.
+struct SpItem {
+    unsigned uv, u, b;
+    int part;
+    bool active;
+};
+
+template <int G>
+__device__ __forceinline__ SpItem sp_item(unsigned g, int M, int B)
+{
+    SpItem it;
+    const unsigned U1 = (unsigned)M + 1;
+    const unsigned gi = blockIdx.x * G + g;
+    it.active = gi < U1 * (unsigned)B;
+    const unsigned gc = it.active ? gi : 0u;
+    it.uv = __builtin_amdgcn_readfirstlane(gc % U1);
+    it.b = __builtin_amdgcn_readfirstlane(gc / U1);
+    it.u = it.uv == (unsigned)M ? 0u : it.uv;
+    it.part = it.uv == 0 ? 1 : (it.uv == (unsigned)M ? 2 : 0);
+    return it;
+}
+
+// Offset of slot s's frequency in a two-row spectrum (see above): row 0 at
+// lo + k2, row 1 at QP + hi - k2.
+template <typename F, int PPT, int QP>
+__device__ __forceinline__ unsigned sp_offset(int s, unsigned ol, unsigned lo, unsigned hi)
+{
+    const bool upper = F::elem_out(s) >= PPT / 2;
+    const unsigned k2 = ol + 64u * F::elem_out(s);
+    return upper ? (unsigned)QP + hi - k2 : lo + k2;
+}
+
+// Spectra of the columns of slabs [s0, s1) (s0, s1 from blockIdx.y and
+// `chunk`) of every model: X[b * nsrc + s] from the columns of
+// R[b * nsrc + s] (laid out [slab][M][ldc]).
+template <typename T, int N>
+__global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
+    col_spectra_ws_kernel(const cx<T> *__restrict__ R, cx<T> *__restrict__ X, int B, int nsrc, int M, int ny,
+                          int ldc, int chunk, const cx<T> *__restrict__ tw, int twlog)
+{
+    using C = WsCfg<T, N>;
+    using F = typename C::FFT;
+    constexpr int PPT = C::PPT, L = C::L, NW = C::NW, G = C::G, GT = C::GT, QP = C::QP;
+    constexpr int GW = 2 * C::CW + NW * C::XW;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned g = wv / NW, w = wv % NW;
+    const unsigned tg = threadIdx.x - g * GT;
+    T *twq = lds;
+    T *gb = lds + C::TWW + (size_t)g * GW;
+    cx<T> *cbuf = reinterpret_cast<cx<T> *>(gb);                        // 2 x N/2 complex
+    T *xch = gb + 2 * C::CW + w * C::XW;
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
+    F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
+    for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) {
+        cbuf[i] = cx<T>{T(0), T(0)};
+        cbuf[N / 2 + i] = cx<T>{T(0), T(0)};
+    }
+    WsTwiddles<T, N, PPT> tws;
+    cx<T> cn[NW > 1 ? NW / 2 : 1];
+    if constexpr (NW > 1) {
+        tws.init(tw, twlog, lane, w);
+        constexpr int LOGN = ilog2<N>::value;
+#pragma unroll
+        for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
+    }
+    unsigned lo, hi;
+    ws_offsets<NW, L>(w, lo, hi);
+    const unsigned ol = ws_out_lane<F>(lane);
+    cx<T> ltw[C::LANE ? 9 : 1];
+    if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
+
+    const SpItem it = sp_item<G>(g, M, B);
+    const unsigned row = spec_row(it.uv, (unsigned)M);
+    const int s0 = (int)blockIdx.y * chunk;
+    const int s1 = min(nsrc, s0 + chunk);
+    cx<T> tail{T(0), T(0)};
+    auto stage_col = [&](int sl, int buf) {
+        stage_column<T, GT>(column(R, (size_t)it.b * nsrc + sl, M, it.u, ldc), cbuf + buf * (N / 2), ny, tg, tail);
+    };
+    if (s0 < s1) {
+        stage_col(s0, 0);
+        put_tail(cbuf, ny, tg, tail);
+    }
+    stage_wait<true>();
+    for (int sl = s0; sl < s1; ++sl) {
+        const int cur = (sl - s0) & 1;
+        if (sl + 1 < s1) stage_col(sl + 1, cur ^ 1);
+        cx<T> v[PPT];
+        const cx<T> *xc = cbuf + cur * (N / 2);
+        if (it.part == 0)
+            form_z<F, T, N, NW, L, PPT, 0>(v, xc, lane, w, cn, tws);
+        else if (it.part == 1)
+            form_z<F, T, N, NW, L, PPT, 1>(v, xc, lane, w, cn, tws);
+        else
+            form_z<F, T, N, NW, L, PPT, 2>(v, xc, lane, w, cn, tws);
+        ws_fft<false, F>(v, xch, lane, twp, twlog, ltw);
+        if (it.active) {
+            cx<T> *dst = X + (((size_t)it.b * nsrc + sl) * (M + 1) + row) * (2 * QP);
+#pragma unroll
+            for (int s = 0; s < PPT; ++s) dst[sp_offset<F, PPT, QP>(s, ol, lo, hi)] = v[s];
+        }
+        if (sl + 1 < s1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
+        stage_wait<true>();
+    }
+}
+
+// Inverse of col_spectra_ws_kernel: the columns of D[b * nsrc + s] (laid out
+// [slab][M][ldc], y < ny written; the two real bins into the fields of
+// packed unit 0) from the spectra X[b * nsrc + s].
+template <typename T, int N>
+__global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
+    col_inverse_ws_kernel(const cx<T> *__restrict__ X, cx<T> *__restrict__ D, int B, int nsrc, int M, int ny,
+                          int ldc, int chunk, const cx<T> *__restrict__ tw, int twlog)
+{
+    using C = WsCfg<T, N>;
+    using F = typename C::FFT;
+    constexpr int PPT = C::PPT, L = C::L, NW = C::NW, G = C::G, GT = C::GT, QP = C::QP;
+    constexpr int GW = 2 * N + NW * C::XW;
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *lds = reinterpret_cast<T *>(smem_raw);
+
+    const unsigned lane = threadIdx.x & 63u;
+    const unsigned wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned g = wv / NW, w = wv % NW;
+    const unsigned tg = threadIdx.x - g * GT;
+    T *twq = lds;
+    T *gb = lds + C::TWW + (size_t)g * GW;
+    T *cre = gb;                                                        // combination: 2N words
+    T *xch = gb + 2 * N + w * C::XW;
+    const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
+    F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
+    WsTwiddles<T, N, PPT> tws;
+    if constexpr (NW > 1) tws.init(tw, twlog, lane, w);
+    unsigned lo, hi;
+    ws_offsets<NW, L>(w, lo, hi);
+    const unsigned ol = ws_out_lane<F>(lane);
+    cx<T> ltw[C::LANE ? 9 : 1];
+    if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
+    __syncthreads();   // stage table
+
+    const SpItem it = sp_item<G>(g, M, B);
+    const unsigned row = spec_row(it.uv, (unsigned)M);
+    const int s0 = (int)blockIdx.y * chunk;
+    const int s1 = min(nsrc, s0 + chunk);
+    for (int sl = s0; sl < s1; ++sl) {
+        const cx<T> *src = X + (((size_t)it.b * nsrc + sl) * (M + 1) + row) * (2 * QP);
+        cx<T> v[PPT];
+#pragma unroll
+        for (int s = 0; s < PPT; ++s) v[s] = src[sp_offset<F, PPT, QP>(s, ol, lo, hi)];
+        ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre, ltw);
+        lds_barrier();
+        if (it.active)
+            ws_store<T, N, NW, L, PPT, GT>(cre, D + (((size_t)it.b * nsrc + sl) * M + it.u) * (size_t)ldc, tg, ny,
+                                           it.part);
+        lds_barrier();
+    }
+}
+
+constexpr int kToepThreads = 256;
+
+// Block of a depth-product launch: blocks are dealt to the eight XCDs in
+// turn, and the output blocks of one position tile go to the same XCD back
+// to back, so that they meet its inputs and spectral layers in one L2.
+// Returns false for the padding blocks of the last round.
+struct ToepBlock {
+    unsigned tile, row, zb;
+};
+
+__device__ __forceinline__ bool toep_block(int ntile, int M, int nzb, ToepBlock &tb)
+{
+    const unsigned lb = blockIdx.x, xcd = lb & 7u, k = lb >> 3;
+    const unsigned zb = k % (unsigned)nzb, tgl = (k / (unsigned)nzb) * 8u + xcd;
+    if (tgl >= (unsigned)ntile * ((unsigned)M + 1u)) return false;
+    tb.tile = tgl % (unsigned)ntile;
+    tb.row = tgl / (unsigned)ntile;
+    tb.zb = zb;
+    return true;
+}
+
+// Depth products of the observation levels at one tile of 32 positions of
+// one spectrum row (lane l: position tile * 32 + l % 32, row l / 32 of the
+// two-row spectrum) of one model (blockIdx.y).  Forward: each wave owns TL
+// consecutive levels o of one component c,
+//   out[b][o][c] = sum_n conj(K^_{c, o + n}) X[b][n],  n < nz;
+// adjoint: each wave owns TL consecutive layers n,
+//   out[b][n] (+)= sum_c sum_t K^_{c, n + t} X[b][t][c],  t < nlev.
+// K^ comes from the window `spec` of nz + nlev - 1 spectral layers
+// ([layer][M+1 rows][Cs][QP], resident order).  The inputs pass through LDS
+// in chunks of JC, and the spectral values of the block's outputs through a
+// ring of KRING layers of the tile (a chunk adds JC layers to it); the next
+// chunk's inputs and layers are loaded into registers while this chunk is
+// computed.  Each thread slides its TL spectral values one layer per input,
+// so a step is one LDS read of an input, one of a spectral value and TL
+// complex multiply-adds.  Forward outputs are [B][nlev][Ct][rows][2][QP]
+// and adjoint inputs likewise (offset by the caller to a group's first
+// component); adjoint outputs [B][nz][rows][2][QP].
+constexpr int kToepJC = 16;
+
+#ifndef GF_TOEP_TL64
+#define GF_TOEP_TL64 8
+#endif
+#ifndef GF_TOEP_TL32
+#define GF_TOEP_TL32 16
+#endif
+#ifndef GF_TOEP_WPE
+#define GF_TOEP_WPE 4
+#endif
+template <typename T>
+constexpr int toep_tl()
+{
+    return sizeof(T) == 8 ? GF_TOEP_TL64 : GF_TOEP_TL32;
+}
+
+template <typename T, int TL>
+constexpr size_t toep_lds_bytes()
+{
+    return (size_t)((kToepThreads / 64) * TL + kToepJC) * 32 * sizeof(T) + (size_t)kToepJC * 64 * sizeof(cx<T>);
+}
+
+template <typename T, int TL, bool ADJ>
+__global__ void __launch_bounds__(kToepThreads) __attribute__((amdgpu_waves_per_eu(GF_TOEP_WPE)))
+    levels_toeplitz_kernel(const cx<T> *__restrict__ X, const T *__restrict__ spec, cx<T> *__restrict__ out,
+                           int nz, int nlev, int M, int QP, int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask,
+                           int ntile, int nzb, int accumulate)
+{
+    constexpr int NWV = kToepThreads / 64, JC = kToepJC;
+    constexpr int KRING = NWV * TL + JC;                 // layers of the tile held in LDS
+    constexpr int KPT = (JC * 32 + kToepThreads - 1) / kToepThreads;   // new spectral values per thread and chunk
+    constexpr int XPT = JC * 64 / kToepThreads;          // inputs per thread and chunk
+    static_assert(JC % TL == 0 && XPT * kToepThreads == JC * 64, "chunk shape");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T *ks = reinterpret_cast<T *>(smem_raw);                            // [KRING][32]
+    cx<T> *xs = reinterpret_cast<cx<T> *>(smem_raw + (size_t)KRING * 32 * sizeof(T));   // [JC][64]
+    ToepBlock tb;
+    if (!toep_block(ntile, M, nzb, tb)) return;
+    const unsigned lane = threadIdx.x & 63u, l32 = lane & 31u;
+    const int wave = (int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const unsigned U1 = (unsigned)M + 1;
+    const unsigned tile = tb.tile, row = tb.row;
+    const unsigned b = blockIdx.y;
+    const unsigned half = lane >> 5;
+    const unsigned pos = tile * 32u + l32;
+    const int nwin = nz + nlev - 1;
+    const size_t kstride = (size_t)U1 * Cs * QP;                        // one spectral layer
+    const int nzb_c = ADJ ? nzb : nzb / Cs;
+    const int c_fwd = ADJ ? 0 : (int)tb.zb / nzb_c;
+    const int o_blk = (int)(tb.zb % (unsigned)nzb_c) * NWV * TL;   // first output of the block
+    const int nout = ADJ ? nz : nlev;
+    const int nin = ADJ ? nlev : nz;
+    const int o0 = o_blk + wave * TL;
+
+    // Staged elements of this thread: spectral values e = threadIdx.x + i *
+    // threads of a chunk's JC new layers (layer e / 32, position e % 32) and
+    // inputs e = threadIdx.x + i * threads (input e / 64, slot e % 64); the
+    // position and slot do not depend on i (threads is a multiple of 64).
+    const unsigned kp32 = min(tile * 32u + (threadIdx.x & 31u), (unsigned)QP - 1u);
+    const unsigned xsl = threadIdx.x & 63u, xp32 = tile * 32u + (xsl & 31u);
+    const bool xok = xp32 < (unsigned)QP;
+    const size_t xslab = (size_t)U1 * 2 * QP;                          // one input slab (values)
+    // spectral value of layer o_blk + r at this thread's position (clamped into the window)
+    auto kval = [&](const T *kc, int r) -> T { return kc[(size_t)min(o_blk + r, nwin - 1) * kstride]; };
+    // input j of this thread's slot, times the factor that turns the real k of
+    // the resident spectrum into the product: forward conj(K^) x, adjoint K^ x,
+    // with K^ = k (real component) or i k (imaginary), and k negated on row 1
+    // for a component odd in y
+    auto xval = [&](const cx<T> *xc, size_t jstride, int j, bool im, bool neg) -> cx<T> {
+        T vr = T(0), vi = T(0);
+        if (j < nin && xok) {
+            const T *src = reinterpret_cast<const T *>(xc + (size_t)j * jstride);
+            vr = src[0];
+            vi = src[1];
+        }
+        if (im) {
+            const T t = vr;
+            vr = ADJ ? -vi : vi;
+            vi = ADJ ? t : -t;
+        }
+        if (neg) {
+            vr = -vr;
+            vi = -vi;
+        }
+        return cx<T>{vr, vi};
+    };
+    constexpr int XROWS = kToepThreads / 64;   // inputs staged per pass of the threads
+
+    cx<T> acc[TL];
+#pragma unroll
+    for (int i = 0; i < TL; ++i) acc[i] = cx<T>{T(0), T(0)};
+    const bool active = o0 < nout;   // waves past the last output only stage and wait
+    const int cbeg = ADJ ? 0 : c_fwd, cend = ADJ ? Cs : c_fwd + 1;
+    for (int c = cbeg; c < cend; ++c) {
+        const bool im = (imag_mask >> c) & 1u, neg = (xsl >> 5) && ((yodd_mask >> c) & 1u);
+        const T *kc = spec + ((size_t)row * Cs + c) * QP + kp32;
+        // this thread's slot of input 0 and the stride between inputs
+        const cx<T> *xc = X + (ADJ ? ((size_t)b * nlev * Ct + c) : (size_t)b * nz) * xslab +
+                          ((size_t)row * 2 + (xsl >> 5)) * QP + xp32;
+        const size_t jstride = ADJ ? (size_t)Ct * xslab : xslab;
+        const int kr0 = (int)(threadIdx.x >> 5), krs = kToepThreads / 32;
+        const int xr0 = (int)(threadIdx.x >> 6);
+        __syncthreads();   // every wave is past its reads of the previous component's buffers
+        // the ring's first KRING - 1 layers and the first chunk of inputs
+        for (int r = kr0; r < KRING - 1; r += krs) ks[r * 32 + (int)(threadIdx.x & 31u)] = kval(kc, r);
+#pragma unroll
+        for (int i = 0; i < XPT; ++i) xs[threadIdx.x + i * kToepThreads] = xval(xc, jstride, xr0 + i * XROWS, im, neg);
+        __syncthreads();
+        T win[TL];
+#pragma unroll
+        for (int i = 0; i < TL - 1; ++i) win[i] = ks[(wave * TL + i) * 32 + l32];
+        int slot = wave * TL + TL - 1;   // ring slot of the layer the next step adds (< KRING)
+        for (int j0 = 0; j0 < nin; j0 += JC) {
+            const bool next = j0 + JC < nin;
+            // the next chunk's inputs and its JC new layers (relative layers
+            // j0 + KRING - 1 ...), into registers
+            cx<T> xp[XPT];
+            T kp[KPT];
+            if (next) {
+#pragma unroll
+                for (int i = 0; i < XPT; ++i) xp[i] = xval(xc, jstride, j0 + JC + xr0 + i * XROWS, im, neg);
+#pragma unroll
+                for (int i = 0; i < KPT; ++i) {
+                    const int r = kr0 + i * krs;
+                    kp[i] = r < JC ? kval(kc, j0 + KRING - 1 + r) : T(0);
+                }
+            }
+            if (active) {
+#pragma unroll 1
+                for (int jj = 0; jj < JC; jj += TL) {
+#pragma unroll
+                    for (int r = 0; r < TL; ++r) {
+                        win[(r + TL - 1) % TL] = ks[slot * 32 + (int)l32];
+                        slot = slot + 1 == KRING ? 0 : slot + 1;
+                        const cx<T> x = xs[(jj + r) * 64 + (int)lane];
+#pragma unroll
+                        for (int i = 0; i < TL; ++i) {
+                            const T k = win[(r + i) % TL];
+                            acc[i].re += k * x.re;
+                            acc[i].im += k * x.im;
+                        }
+                    }
+                }
+            }
+            if (next) {
+                __syncthreads();   // every wave is past its reads of this chunk
+#pragma unroll
+                for (int i = 0; i < XPT; ++i) xs[threadIdx.x + i * kToepThreads] = xp[i];
+#pragma unroll
+                for (int i = 0; i < KPT; ++i) {
+                    const int r = kr0 + i * krs;
+                    if (r < JC) ks[((j0 + KRING - 1 + r) % KRING) * 32 + (int)(threadIdx.x & 31u)] = kp[i];
+                }
+                __syncthreads();
+            }
+        }
+    }
+    if (pos < (unsigned)QP) {
+#pragma unroll
+        for (int i = 0; i < TL; ++i) {
+            const int o = o0 + i;
+            if (o < nout) {
+                const size_t slab = ADJ ? (size_t)b * nz + o : ((size_t)b * nlev + o) * Ct + c_fwd;
+                cx<T> *dst = out + ((slab * U1 + row) * 2 + half) * (size_t)QP + pos;
+                cx<T> v = acc[i];
+                if (ADJ && accumulate) v = add(*dst, v);
+                *dst = v;
+            }
+        }
+    }
+}
+
 // Plan time: full-length column FFT of the row-transformed kernel fields
 // (double), keeping one real per frequency of the quarter plane.  Virtual
 // units as in the adjoint.
@@ -1650,6 +2049,52 @@ static int run_levels_adj(const void *R, const void *spec, void *Gout, int B, in
     } else {
         return -2;
     }
+}
+
+template <typename T, int N>
+static int run_spectra(bool inverse, const void *src, void *dst, int B, int nsrc, int M, int ny, int ldc,
+                       const void *tw, int twlog, hipStream_t st)
+{
+    if constexpr (use_ws<N>()) {
+        using C = WsCfg<T, N>;
+        constexpr int chunk = 8;
+        const long nblk = ((long)(M + 1) * B + C::G - 1) / C::G;
+        const long nchunk = (nsrc + chunk - 1) / chunk;
+        if (nblk < 1 || nchunk < 1) return 0;
+        if (!inverse) {
+            const size_t lds = ((size_t)C::G * (2 * C::CW + C::NW * C::XW) + C::TWW) * sizeof(T);
+            if (lds > lds_limit()) return -3;
+            hipLaunchKernelGGL((col_spectra_ws_kernel<T, N>), dim3((unsigned)nblk, (unsigned)nchunk),
+                               dim3(C::THREADS), lds, st, (const cx<T> *)src, (cx<T> *)dst, B, nsrc, M, ny, ldc,
+                               chunk, (const cx<T> *)tw, twlog);
+        } else {
+            const size_t lds = ((size_t)C::G * (2 * N + C::NW * C::XW) + C::TWW) * sizeof(T);
+            if (lds > lds_limit()) return -3;
+            hipLaunchKernelGGL((col_inverse_ws_kernel<T, N>), dim3((unsigned)nblk, (unsigned)nchunk),
+                               dim3(C::THREADS), lds, st, (const cx<T> *)src, (cx<T> *)dst, B, nsrc, M, ny, ldc,
+                               chunk, (const cx<T> *)tw, twlog);
+        }
+        return hipGetLastError() == hipSuccess ? 0 : -1;
+    } else {
+        return -2;
+    }
+}
+
+template <typename T, bool ADJ>
+static int run_toep(const void *X, const void *spec, void *out, int B, int nz, int nlev, int M, int QP, int Cs, int Ct,
+                    unsigned im, unsigned yo, bool accumulate, hipStream_t st)
+{
+    constexpr int TL = toep_tl<T>(), per = (kToepThreads / 64) * TL;
+    const int ntile = (QP + 31) / 32;
+    const int nzb = ADJ ? (nz + per - 1) / per : Cs * ((nlev + per - 1) / per);
+    const long ntt = (long)ntile * (M + 1);
+    const long nblk = ((ntt + 7) / 8) * 8 * nzb;
+    const size_t lds = toep_lds_bytes<T, TL>();
+    if (lds > lds_limit()) return -3;
+    hipLaunchKernelGGL((levels_toeplitz_kernel<T, TL, ADJ>), dim3((unsigned)nblk, (unsigned)B), dim3(kToepThreads),
+                       lds, st, (const cx<T> *)X, (const T *)spec, (cx<T> *)out, nz, nlev, M, QP, Cs, Ct, im, yo,
+                       ntile, nzb, accumulate ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename TO, int N>
@@ -1970,6 +2415,69 @@ int col_forward_groups(bool fp64, int py)
         return 1;
     }
 #undef CASE
+}
+
+int launch_col_spectra(bool fp64, int py, const void *R, void *X, int B, int nsrc, int M, int ny, int ldc,
+                       const void *tw, int twlog, hipStream_t st)
+{
+    if (B < 1 || nsrc < 0 || ny < 1 || 2 * ny > py || ldc < ny) return -2;
+#define CASE(NN)                                                                                          \
+    case NN:                                                                                              \
+        return fp64 ? run_spectra<double, NN>(false, R, X, B, nsrc, M, ny, ldc, tw, twlog, st)           \
+                    : run_spectra<float, NN>(false, R, X, B, nsrc, M, ny, ldc, tw, twlog, st);
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return -2;
+    }
+#undef CASE
+}
+
+int launch_col_inverse(bool fp64, int py, const void *X, void *D, int B, int nsrc, int M, int ny, int ldc,
+                       const void *tw, int twlog, hipStream_t st)
+{
+    if (B < 1 || nsrc < 0 || ny < 1 || 2 * ny > py || ldc < ny) return -2;
+#define CASE(NN)                                                                                          \
+    case NN:                                                                                              \
+        return fp64 ? run_spectra<double, NN>(true, X, D, B, nsrc, M, ny, ldc, tw, twlog, st)            \
+                    : run_spectra<float, NN>(true, X, D, B, nsrc, M, ny, ldc, tw, twlog, st);
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return -2;
+    }
+#undef CASE
+}
+
+bool col_spectra_supported(int py)
+{
+#define CASE(NN) \
+    case NN:     \
+        return use_ws<NN>();
+    switch (py) {
+        GF_COL_SIZES(CASE)
+    default:
+        return false;
+    }
+#undef CASE
+}
+
+int launch_levels_forward(bool fp64, int py, const void *X, const void *spec, void *Dh, int B, int nz, int nlev, int M,
+                          int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, hipStream_t st)
+{
+    const int QP = spec_row_pitch(fp64, py);
+    if (QP <= 0 || B < 1 || nz < 1 || nlev < 1 || Cs < 1 || Cs > kColMaxSpec || Ct < Cs) return -2;
+    return fp64 ? run_toep<double, false>(X, spec, Dh, B, nz, nlev, M, QP, Cs, Ct, imag_mask, yodd_mask, false, st)
+                : run_toep<float, false>(X, spec, Dh, B, nz, nlev, M, QP, Cs, Ct, imag_mask, yodd_mask, false, st);
+}
+
+int launch_levels_adjoint(bool fp64, int py, const void *Rh, const void *spec, void *Gh, int B, int nz, int nlev, int M,
+                          int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, bool accumulate, hipStream_t st)
+{
+    const int QP = spec_row_pitch(fp64, py);
+    if (QP <= 0 || B < 1 || nz < 1 || nlev < 1 || Cs < 1 || Cs > kColMaxSpec || Ct < Cs) return -2;
+    return fp64 ? run_toep<double, true>(Rh, spec, Gh, B, nz, nlev, M, QP, Cs, Ct, imag_mask, yodd_mask, accumulate, st)
+                : run_toep<float, true>(Rh, spec, Gh, B, nz, nlev, M, QP, Cs, Ct, imag_mask, yodd_mask, accumulate, st);
 }
 
 }  // namespace gf

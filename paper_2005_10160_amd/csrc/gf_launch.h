@@ -51,9 +51,10 @@ struct KgenGeom {
 //   in       base of source rows; row (b, src, y) at in + ((b*src_per_b + src)*rows + y)*row_len
 //   lin      nonzero entries per row (<= px); the rest of each row is zero
 //   rows     rows per slab; nsub slabs per batch item; nbatch items
+//   out_bslabs  slabs between batch items of out (0: nsub, packed)
 int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int rows, int ldc,
                    int nsub, int src_per_b, int nbatch, const RowCombo &cmb, void *out, const void *tw,
-                   int twlog, hipStream_t st);
+                   int twlog, hipStream_t st, long out_bslabs = 0);
 
 // Inverse row transform: X(b,o,y)[u] = sum_split sum_i w[o][i] D[split][b][src[o][i]][u][y],
 // then real rows of length px, of which the first nx_out are written, times
@@ -108,6 +109,27 @@ int launch_col_adjoint_levels(bool fp64, int py, const void *R, const void *spec
                               int ny, int ldc, int Cs, int nlev, int nsplit, int lps, const NyqSplit &nq,
                               unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog, hipStream_t st);
 bool col_levels_supported(bool fp64, int py);
+
+// Observation levels as a Toeplitz product in depth.  A column's spectrum
+// is two rows of QP values (row 0: ky = q, row 1: ky = py - q, both at the
+// resident position of q); a slab is [M+1 rows][2][QP] complex.
+// Spectra X[b*nsrc + s] of the columns of R[b*nsrc + s] (slabs [M][ldc]).
+int launch_col_spectra(bool fp64, int py, const void *R, void *X, int B, int nsrc, int M, int ny, int ldc,
+                       const void *tw, int twlog, hipStream_t st);
+// The inverse: columns D[b*nsrc + s] (y < ny) from the spectra X[b*nsrc + s].
+int launch_col_inverse(bool fp64, int py, const void *X, void *D, int B, int nsrc, int M, int ny, int ldc,
+                       const void *tw, int twlog, hipStream_t st);
+// Whether the two above exist for transform length py (the wave-split lengths).
+bool col_spectra_supported(int py);
+// Dh[b][o][c] = sum_n conj(K^_{c,o+n}) X[b][n] for o < nlev, n < nz; spec is
+// the window of nz + nlev - 1 spectral layers of one group of Cs spectra;
+// Dh holds Ct slots per level (offset by the caller to the group's first).
+int launch_levels_forward(bool fp64, int py, const void *X, const void *spec, void *Dh, int B, int nz, int nlev, int M,
+                          int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, hipStream_t st);
+// Gh[b][n] (+)= sum_c sum_t K^_{c,n+t} Rh[b][t][c] for n < nz, t < nlev; Rh holds
+// Ct slots per level (offset to the group's first), Gh is added to when accumulate.
+int launch_levels_adjoint(bool fp64, int py, const void *Rh, const void *spec, void *Gh, int B, int nz, int nlev, int M,
+                          int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, bool accumulate, hipStream_t st);
 
 // Plan time: column FFT of the row-transformed kernel fields and extraction
 // of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).

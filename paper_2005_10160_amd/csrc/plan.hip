@@ -101,6 +101,12 @@ std::unordered_map<void *, size_t> g_live;
 size_t g_live_bytes = 0;
 long g_fail_countdown = 0;
 
+// Test hook (gf_debug_level_path): how plans created afterwards run their
+// observation levels (0: by their byte estimate, 1: column passes, 2: the
+// Toeplitz product), and a cap on the Toeplitz path's levels per chunk.
+std::mutex g_level_mu;
+int g_level_path = 0, g_level_chunk = 0;
+
 hipError_t dev_malloc(void **ptr, size_t bytes)
 {
     std::lock_guard<std::mutex> lk(g_alloc_mu);
@@ -192,6 +198,43 @@ struct gf_plan {
     int levels_per_pass() const { return levels_blocked() ? std::min(nt, 6 / n_spec) : 1; }
     // slots of the forward column pass's outputs (D and Dny)
     int fwd_slots() const { return levels_per_pass() * n_spec; }
+    // Observation levels as a Toeplitz product in depth (the column
+    // transforms of the density or residuals once, the products of every
+    // level per frequency, the inverse transforms once) where that moves
+    // fewer bytes than column passes per level (or per block of levels).
+    // Estimated for one model, so that the choice does not depend on the
+    // batch.
+    size_t spec_layer_bytes() const { return elem() * (size_t)U * n_spec * QP; }
+    size_t col_slab_bytes() const { return celem() * (size_t)M * ldc; }    // one [M][ldc] slab
+    size_t sp_slab_bytes() const { return celem() * (size_t)U * 2 * QP; }  // one two-row spectrum slab
+    // Levels per chunk of the Toeplitz path: the chunk's output spectra and
+    // columns within 32 GiB per model.
+    int toep_chunk_default() const
+    {
+        const size_t per_level = (size_t)n_spec * (sp_slab_bytes() + col_slab_bytes());
+        const size_t budget = (size_t)32 << 30;
+        return (int)std::max<size_t>(1, std::min<size_t>((size_t)nt, budget / per_level));
+    }
+    bool toeplitz_cheaper() const
+    {
+        if (nt < 2 || !gf::col_spectra_supported(py)) return false;
+        const double R = (double)nz * col_slab_bytes(), layer = (double)spec_layer_bytes();
+        double old_bytes;
+        if (levels_blocked()) {
+            const int per = levels_per_pass();
+            old_bytes = (double)((nt + per - 1) / per) * (R + (nz + per - 1) * layer);
+        } else {
+            old_bytes = (double)nt * (ngrp * R + nz * layer);
+        }
+        const int tc = toep_chunk_default(), nch = (nt + tc - 1) / tc;
+        const double X = (double)nz * sp_slab_bytes();
+        const double new_bytes = X + nch * (ngrp * X + (nz + tc - 1) * layer) + 2.0 * nt * n_spec * sp_slab_bytes();
+        return new_bytes < old_bytes;
+    }
+    bool toep = false;              // decided at creation
+    int toep_tc = 1;
+    bool levels_toeplitz() const { return toep; }
+    int toep_chunk() const { return toep_tc; }
     unsigned grp_bits(unsigned m, int g) const { return (m >> grp_c0[g]) & ((1u << grp_cs[g]) - 1u); }
     size_t elem() const { return fp64() ? sizeof(double) : sizeof(float); }
     size_t celem() const { return 2 * elem(); }
@@ -271,6 +314,12 @@ struct gf_plan {
     }
     size_t ws_bytes(int op, int B) const
     {
+        if (levels_toeplitz()) {
+            // forward: R [B][nz] cols, X [B][nz] spectra, Dh [B][tc][n_spec] spectra, D [B][tc][n_spec] cols;
+            // adjoint: R [B][tc][n_spec] cols, X [B][tc][n_spec] spectra, Gh [B][nz] spectra, Gt [B][nz] cols
+            const size_t tc = (size_t)toep_chunk();
+            return (size_t)B * (nz + tc * n_spec) * (col_slab_bytes() + sp_slab_bytes());
+        }
         if (op == GF_OP_FORWARD) {
             int S, l;
             fwd_split(B, &S, &l);
@@ -433,6 +482,15 @@ const char *gf_status_string(gf_status s)
 
 const char *gf_last_error(void) { return g_err.c_str(); }
 
+gf_status gf_debug_level_path(int mode, int max_chunk)
+{
+    if (mode < 0 || mode > 2 || max_chunk < 0) return fail(GF_EINVAL, "bad level path %d / chunk %d", mode, max_chunk);
+    std::lock_guard<std::mutex> lk(g_level_mu);
+    g_level_path = mode;
+    g_level_chunk = max_chunk;
+    return GF_OK;
+}
+
 gf_status gf_debug_fail_alloc(int nth)
 {
     if (nth < 0) return fail(GF_EINVAL, "nth must be >= 0");
@@ -518,6 +576,13 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     for (int g = 0; g < p->ngrp; ++g) {
         p->grp_c0[g] = g * p->gmax;
         p->grp_cs[g] = std::min(p->gmax, p->n_spec - p->grp_c0[g]);
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_level_mu);
+        if (nt > 1 && gf::col_spectra_supported(p->py))
+            p->toep = g_level_path == 2 || (g_level_path == 0 && p->toeplitz_cheaper());
+        p->toep_tc = p->toep_chunk_default();
+        if (g_level_chunk > 0) p->toep_tc = std::min(p->toep_tc, g_level_chunk);
     }
     std::memset(&p->out_combo, 0, sizeof(p->out_combo));
     for (int o = 0; o < p->n_out; ++o) {
@@ -690,6 +755,8 @@ gf_status gf_plan_get_info(const gf_plan *p, gf_plan_info_t *info)
     info->spectra_bytes = p->spec_bytes;
     info->internal_workspace_bytes = p->iws_bytes;
     info->plan_ms = p->plan_ms;
+    info->level_path = p->nt < 2 ? 0 : (p->toep ? 3 : (p->levels_blocked() ? 2 : 1));
+    info->level_chunk = p->toep ? p->toep_tc : 0;
     return GF_OK;
 }
 
@@ -746,6 +813,47 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
     const size_t plane = (size_t)p->nx * p->ny;
     const long dstride = (long)p->nt * p->n_out * (long)plane;
     const double scale = kGrav / ((double)p->py * p->M);
+    if (p->levels_toeplitz()) {
+        // the density spectra once; per chunk of levels the depth products of
+        // every group, the inverse column transforms and the inverse rows of
+        // each level
+        const int tcm = p->toep_chunk();
+        char *X = R + p->col_slab_bytes() * (size_t)batch * p->nz;
+        char *Dh = X + p->sp_slab_bytes() * (size_t)batch * p->nz;
+        char *Dc = Dh + p->sp_slab_bytes() * (size_t)batch * tcm * p->n_spec;
+        if (gf::launch_col_spectra(p->fp64(), p->py, R, X, batch, p->nz, p->M, p->ny, p->ldc, p->tw, p->twlog, st) != 0)
+            return fail(GF_EDEVICE, "column spectra launch: %s", hipGetErrorString(hipGetLastError()));
+        const gf::NyqSplit none{nullptr, 0, 0};
+        for (int t0 = 0; t0 < p->nt; t0 += tcm) {
+            const int tc = std::min(tcm, p->nt - t0);
+            for (int gr = 0; gr < p->ngrp; ++gr)
+                if (gf::launch_levels_forward(p->fp64(), p->py, X, p->spec_window(gr, t0),
+                                              Dh + p->sp_slab_bytes() * (size_t)p->grp_c0[gr], batch, p->nz, tc, p->M,
+                                              p->grp_cs[gr], p->n_spec, p->grp_bits(p->imag_mask, gr),
+                                              p->grp_bits(p->yodd_mask, gr), st) != 0)
+                    return fail(GF_EDEVICE, "depth product launch: %s", hipGetErrorString(hipGetLastError()));
+            const int slots = tc * p->n_spec;
+            if (gf::launch_col_inverse(p->fp64(), p->py, Dh, Dc, batch, slots, p->M, p->ny, p->ldc, p->tw, p->twlog,
+                                       st) != 0)
+                return fail(GF_EDEVICE, "inverse column launch: %s", hipGetErrorString(hipGetLastError()));
+            if (t0 + tc == p->nt) mark(p, GF_OP_FORWARD, 2, st);
+            // the inverse rows of every level of the chunk in one launch per
+            // model (levels are consecutive items of n_spec slabs in Dc and of
+            // n_out planes in d); one launch for all models when the chunk is
+            // every level
+            const int nitems = tc == p->nt ? batch * tc : tc;
+            for (int b0 = 0; b0 < batch; b0 += nitems / tc) {
+                if (gf::launch_row_c2r(p->fp64(), p->px, Dc + p->col_slab_bytes() * (size_t)b0 * slots,
+                                       (long)nitems * p->n_spec * p->M * p->ldc, 1, p->n_spec, p->ny, p->ldc, p->n_out,
+                                       nitems, p->out_combo, none,
+                                       (char *)d + p->elem() * ((size_t)b0 * p->nt + t0) * p->n_out * plane, p->nx,
+                                       scale, p->tw, p->twlog, st, (long)p->n_out * plane, false) != 0)
+                    return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+            }
+        }
+        mark(p, GF_OP_FORWARD, 3, st);
+        return GF_OK;
+    }
     if (p->levels_blocked()) {
         // passes of up to levels_per_pass() levels; level j of a pass is
         // slots [j Cs, (j+1) Cs) of its D and Dny
@@ -838,6 +946,51 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
     const double scale = kGrav / ((double)p->py * p->M);
     const gf::NyqSplit none{nullptr, 0, 0};
     mark(p, GF_OP_ADJOINT, 0, st);
+    if (p->levels_toeplitz()) {
+        // per chunk of levels: the residuals' row transforms (one launch per
+        // level), their column spectra, and the depth products of every group
+        // summed into the layer spectra; then the inverse column transforms
+        // and rows once
+        const int tcm = p->toep_chunk();
+        const size_t rs = p->col_slab_bytes(), ss = p->sp_slab_bytes();
+        char *Rl = (char *)workspace;
+        char *Xr = Rl + rs * (size_t)batch * tcm * p->n_spec;
+        char *Gh = Xr + ss * (size_t)batch * tcm * p->n_spec;
+        char *Gc = Gh + ss * (size_t)batch * p->nz;
+        for (int t0 = 0; t0 < p->nt; t0 += tcm) {
+            const int tc = std::min(tcm, p->nt - t0);
+            const int slots = tc * p->n_spec;
+            // the row transforms of every level of the chunk in one launch per
+            // model (levels are consecutive items of n_out planes in r and of
+            // n_spec slabs in Rl); one launch for all models when the chunk is
+            // every level
+            const int nitems = tc == p->nt ? batch * tc : tc;
+            for (int b0 = 0; b0 < batch; b0 += nitems / tc)
+                if (gf::launch_row_r2c(p->fp64(), p->px,
+                                       (const char *)r + p->elem() * ((size_t)b0 * p->nt + t0) * p->n_out * plane, p->nx,
+                                       p->nx, p->ny, p->ldc, p->n_spec, p->n_out, nitems, p->in_combo,
+                                       Rl + rs * (size_t)b0 * slots, p->tw, p->twlog, st) != 0)
+                    return fail(GF_EDEVICE, "row transform launch: %s", hipGetErrorString(hipGetLastError()));
+            if (t0 == 0) mark(p, GF_OP_ADJOINT, 1, st);
+            if (gf::launch_col_spectra(p->fp64(), p->py, Rl, Xr, batch, slots, p->M, p->ny, p->ldc, p->tw, p->twlog,
+                                       st) != 0)
+                return fail(GF_EDEVICE, "column spectra launch: %s", hipGetErrorString(hipGetLastError()));
+            for (int gr = 0; gr < p->ngrp; ++gr)
+                if (gf::launch_levels_adjoint(p->fp64(), p->py, Xr + ss * (size_t)p->grp_c0[gr], p->spec_window(gr, t0),
+                                              Gh, batch, p->nz, tc, p->M, p->grp_cs[gr], p->n_spec,
+                                              p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr),
+                                              t0 > 0 || gr > 0, st) != 0)
+                    return fail(GF_EDEVICE, "depth product launch: %s", hipGetErrorString(hipGetLastError()));
+        }
+        if (gf::launch_col_inverse(p->fp64(), p->py, Gh, Gc, batch, p->nz, p->M, p->ny, p->ldc, p->tw, p->twlog, st) != 0)
+            return fail(GF_EDEVICE, "inverse column launch: %s", hipGetErrorString(hipGetLastError()));
+        mark(p, GF_OP_ADJOINT, 2, st);
+        if (gf::launch_row_c2r(p->fp64(), p->px, Gc, (long)batch * p->nz * p->M * p->ldc, 1, p->nz, p->ny, p->ldc,
+                               p->nz, batch, ident, none, g, p->nx, scale, p->tw, p->twlog, st, 0, false) != 0)
+            return fail(GF_EDEVICE, "inverse row transform launch: %s", hipGetErrorString(hipGetLastError()));
+        mark(p, GF_OP_ADJOINT, 3, st);
+        return GF_OK;
+    }
     if (p->levels_blocked()) {
         // passes of up to levels_per_pass() levels: one row transform of the
         // pass's residual planes into level-major slots, one column pass

@@ -129,7 +129,7 @@ template <typename T, int M>
 __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
     __attribute__((amdgpu_waves_per_eu(RowCfgF<T, M>::WAVES_PER_EU)))
     row_r2c_kernel(const T *__restrict__ in, long row_len, int lin, int rows, int ldc, int nsub, int src_per_b,
-                   long nrows_total, RowCombo cmb, cx<T> *__restrict__ out,
+                   long nrows_total, RowCombo cmb, cx<T> *__restrict__ out, long out_bslabs,
                    const cx<T> *__restrict__ tw, int twlog)
 {
     using C = RowCfgF<T, M>;
@@ -260,9 +260,10 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
             const cx<T> w = twiddle<T, false>(tw, twlog, u, logpx);
             X = add(xe, mul(w, xo));
         }
-        const long slab = grr / rows;
+        const long slab = grr / rows;   // b * nsub + s, written to slab b * out_bslabs + s
+        const long oslab = (slab / nsub) * out_bslabs + slab % nsub;
         const int y = (int)(grr % rows);
-        out[(slab * M + u) * (long)ldc + y] = X;
+        out[(oslab * M + u) * (long)ldc + y] = X;
     }
 }
 
@@ -416,7 +417,7 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
 
 template <typename T, int M>
 static int run_r2c(const void *in, long row_len, int lin, int rows, int ldc, int nsub, int src_per_b,
-                   int nbatch, const RowCombo &cmb, void *out, const void *tw, int twlog,
+                   int nbatch, const RowCombo &cmb, void *out, long out_bslabs, const void *tw, int twlog,
                    hipStream_t st)
 {
     using C = RowCfgF<T, M>;
@@ -427,7 +428,7 @@ static int run_r2c(const void *in, long row_len, int lin, int rows, int ldc, int
     if (lds > lds_limit()) return -3;
     hipLaunchKernelGGL((row_r2c_kernel<T, M>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
                        (const T *)in, row_len, lin, rows, ldc, nsub, src_per_b, nrows, cmb, (cx<T> *)out,
-                       (const cx<T> *)tw, twlog);
+                       out_bslabs > 0 ? out_bslabs : (long)nsub, (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -454,15 +455,15 @@ static int run_c2r(const void *D, long split_stride, int nsplit, int nsrc, int r
 
 int launch_row_r2c(bool fp64, int px, const void *in, long row_len, int lin, int rows, int ldc,
                    int nsub, int src_per_b, int nbatch, const RowCombo &cmb, void *out, const void *tw,
-                   int twlog, hipStream_t st)
+                   int twlog, hipStream_t st, long out_bslabs)
 {
     const int M = px / 2;
 #define CASE(MM)                                                                              \
     case MM:                                                                                  \
         return fp64 ? run_r2c<double, MM>(in, row_len, lin, rows, ldc, nsub, src_per_b, nbatch, cmb, \
-                                          out, tw, twlog, st)                                 \
+                                          out, out_bslabs, tw, twlog, st)                     \
                     : run_r2c<float, MM>(in, row_len, lin, rows, ldc, nsub, src_per_b, nbatch, cmb,  \
-                                         out, tw, twlog, st);
+                                         out, out_bslabs, tw, twlog, st);
     switch (M) {
         GF_ROW_SIZES(CASE)
     default:

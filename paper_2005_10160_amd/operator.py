@@ -86,6 +86,8 @@ class Plan:
         self.n_out = info.n_out
         self.n_levels = info.n_levels
         self.col_groups = info.col_groups
+        self.level_path = info.level_path
+        self.level_chunk = info.level_chunk
         # one data plane per observation level
         self.data_shape = ((self.n_levels,) if self.n_levels > 1 else ()) + (self.n_out, self.ny, self.nx)
         self.out_components = tuple(COMPONENTS[i] for i in range(len(COMPONENTS)) if self.mask >> i & 1)

@@ -449,7 +449,13 @@ class GpuExecutor:
         per = 2 * self.elem * ux * (key.ny + 1)
         fwd = per * batch * (key.nz + splits * slots) + self.elem * splits * batch * slots * (key.ny + 1)
         adj = per * batch * chunk * (slots + groups * key.nz)
-        return max(fwd, adj)
+        # levels as a Toeplitz product in depth: column slabs and two-row
+        # spectrum slabs for the layers and for every level's components
+        toep = 0
+        if key.levels > 1:
+            py = _circulant(key.ny)
+            toep = batch * (key.nz + key.levels * nspec) * 2 * self.elem * ux * ((key.ny + 1) + (py + 8))
+        return max(fwd, adj, toep)
 
     def is_resident(self, key):
         with self.build_cv:

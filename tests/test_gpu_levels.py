@@ -247,3 +247,70 @@ def test_levels_medium_prisms_full_field(gf, orc):
         e = rel(d[t, 0], want)
         note("levels prism field level %d gz rel %.2e" % (t, e))
         assert e <= TOL["f64"], (t, e)
+
+
+def _plan_with_path(gf, g, levels, mask, prec, mode, chunk=0):
+    from paper_2005_10160_amd import _native
+    lib = _native.load()
+    assert lib.gf_debug_level_path(mode, chunk) == _native.GF_OK
+    try:
+        return gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, mask, prec)
+    finally:
+        lib.gf_debug_level_path(0, 0)
+
+
+# the Toeplitz product in depth against the column passes: wave-split
+# column lengths 256 (one wave), 512, 1024, 2048 and 4096 (eight points a
+# lane in FP64), one to eight spectra (two column-pass groups), more
+# layers than one staging chunk of the depth products, level chunks
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("nx,ny,nz,levels,mask,chunk", [
+    (40, 100, 6, 6, 0x1, 0),
+    (40, 130, 7, 9, 0x1, 4),
+    (24, 300, 5, 5, 0x1FF, 2),
+    (30, 130, 70, 4, 0x3F, 0),
+    (16, 520, 9, 7, 0x181, 3),
+    (6, 1100, 3, 3, 0x41, 0),
+])
+def test_levels_toeplitz_path(gf, orc, nx, ny, nz, levels, mask, chunk, prec):
+    """The levels as a Toeplitz product in depth (column spectra once, the
+    depth products per frequency, the inverse transforms once) give the
+    operator of the per-level column passes: forward and adjoint agree to
+    rounding, batch = single bitwise, the dot-product identity holds, and
+    a sample of stations matches the oracle."""
+    g = Geometry(nx, ny, nz, 20.0, 25.0, 15.0, 7.0)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    note("toeplitz levels %s levels %d mask 0x%x chunk %d %s" % (g, levels, mask, chunk, prec))
+    pa = _plan_with_path(gf, g, levels, mask, prec, 1)
+    pb = _plan_with_path(gf, g, levels, mask, prec, 2, chunk)
+    assert pa.level_path in (1, 2) and pb.level_path == 3
+    assert pb.level_chunk == (min(chunk, levels) if chunk else levels)
+    rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=s, block=None) for s in (64, 65)])
+    x = torch.from_numpy(rho).to("cuda", dt)
+    da = pa.forward(x).double().cpu().numpy()
+    db = pb.forward(x).double().cpu().numpy()
+    close = 1e-12 if prec == "f64" else 2e-6
+    for t in range(levels):
+        for c in range(da.shape[2]):
+            assert rel(db[:, t, c], da[:, t, c]) <= close, (t, c, rel(db[:, t, c], da[:, t, c]))
+    for b in range(2):
+        assert np.array_equal(db[b], pb.forward(x[b]).double().cpu().numpy()), b
+    rng = np.random.default_rng(66)
+    r = torch.from_numpy(rng.standard_normal(da.shape)).to("cuda", dt)
+    ga = pa.adjoint(r).double().cpu().numpy()
+    gb = pb.adjoint(r).double().cpu().numpy()
+    assert rel(gb, ga) <= close, rel(gb, ga)
+    for b in range(2):
+        assert np.array_equal(gb[b], pb.adjoint(r[b]).double().cpu().numpy()), b
+    rn = r.double().cpu().numpy()
+    lhs, rhs = float(np.sum(db * rn)), float(np.sum(rho * gb))
+    assert abs(lhs - rhs) <= DOT[prec] * np.linalg.norm(db) * np.linalg.norm(rn), (lhs, rhs)
+    comps = [c for c in range(9) if mask >> c & 1]
+    st = np.array([(0, 0), (g.nx - 1, g.ny - 1), (g.nx // 2, g.ny // 2), (g.nx // 3, (2 * g.ny) // 3)])
+    want = orc.forward_levels(g, rho[0], levels, st)
+    for t in (0, levels - 1):
+        for i, c in enumerate(comps):
+            e = rel(db[0, t, i][st[:, 1], st[:, 0]], want[t, :, c])
+            assert e <= TOL[prec], (t, NAMES[c], e)
+    pa.close()
+    pb.close()
