@@ -18,6 +18,7 @@
 #include <type_traits>
 
 #include "gf_fft.h"
+#include "gf_lane.h"
 #include "gf_launch.h"
 
 namespace gf {
@@ -463,164 +464,6 @@ constexpr bool use_ws() { return N >= 256; }
 template <typename T, int N>
 constexpr int ws_waves() { return use_ws<N>() ? N / (64 * ws_ppt<T, N>()) : 1; }
 
-// In-register transform of one wave: 256 points, four a lane, radix 4
-// (gfx950 cross-lane moves instead of LDS exchanges).  The point index has
-// eight bits: a lane's register slot holds two, the lane index six.  Each
-// radix-4 stage works on the slot bits; between stages the slot bits trade
-// places with two lane bits: v_permlane32_swap / v_permlane16_swap for lane
-// bits 5 and 4, DPP for bits 3-0 (bank-masked row shifts, quad permutes).
-// Forward (decimation in frequency, stages on index bits 7-6, 5-4, 3-2,
-// 1-0): slot s of lane l holds n = l + 64 s on input and
-// k = rev(l) + 64 s on output, rev(l) = l/16 + 4 ((l/4) mod 4) + 16 (l mod 4).
-// Inverse (unnormalised): input in the forward's output layout, the lane
-// bits traded in the reverse order, output m = l + 64 s.
-template <typename T>
-struct LaneFFT {
-    static constexpr int lds_words() { return 0; }
-    static constexpr int stw_entries() { return 0; }
-    static constexpr int elem_in(int s) { return s; }
-    static constexpr int elem_out(int s) { return s; }
-    __device__ static void load_stage_table(T *, const cx<T> *, int, unsigned, unsigned) {}
-};
-
-template <typename F>
-struct is_lane_fft { static constexpr bool value = false; };
-template <typename T>
-struct is_lane_fft<LaneFFT<T>> { static constexpr bool value = true; };
-
-// Lane index of the forward output position: slot s of lane l holds
-// frequency ws_out_lane(l) + 64 s.
-template <typename F>
-__device__ __forceinline__ unsigned ws_out_lane(unsigned l)
-{
-    if constexpr (is_lane_fft<F>::value) return (l >> 4) + 4u * ((l >> 2) & 3u) + 16u * (l & 3u);
-    else return l;
-}
-
-template <int CTRL, int BANK = 0xF>
-__device__ __forceinline__ unsigned dpp_word(unsigned old, unsigned x)
-{
-    return (unsigned)__builtin_amdgcn_update_dpp((int)old, (int)x, CTRL, 0xF, BANK, false);
-}
-
-// Trade the register bit that tells a from b with lane bit B, for one
-// 32-bit word: afterwards a holds the values whose lane bit B was 0 (at
-// lane bit B = the old register bit), b those whose lane bit B was 1.
-// `hi` is lane bit B of this lane.
-template <int B>
-__device__ __forceinline__ void xswap(unsigned &a, unsigned &b, bool hi)
-{
-    if constexpr (B == 5) {
-        const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
-        a = r[0];
-        b = r[1];
-    } else if constexpr (B == 4) {
-        const auto r = __builtin_amdgcn_permlane16_swap(a, b, false, false);
-        a = r[0];
-        b = r[1];
-    } else if constexpr (B == 3 || B == 2) {
-        // row shifts by 2^B written only to the banks (groups of four lanes)
-        // whose lane bit B is set (a: from lane l - 2^B of b) or clear (b:
-        // from lane l + 2^B of a): banks 2, 3 / 0, 1 for bit 3, 1, 3 / 0, 2
-        // for bit 2
-        constexpr int SHR = 0x110 + (1 << B), SHL = 0x100 + (1 << B);
-        constexpr int SET = B == 3 ? 0xC : 0xA, CLR = B == 3 ? 0x3 : 0x5;
-        const unsigned na = dpp_word<SHR, SET>(a, b), nb = dpp_word<SHL, CLR>(b, a);
-        a = na;
-        b = nb;
-    } else {
-        // lane l ^ 1 or l ^ 2 within the quad, then a select on the lane bit
-        constexpr int Q = B == 0 ? 0xB1 : 0x4E;
-        const unsigned pa = dpp_word<Q>(0u, a), pb = dpp_word<Q>(0u, b);
-        const unsigned na = hi ? pb : a, nb = hi ? b : pa;
-        a = na;
-        b = nb;
-    }
-}
-
-template <int B, typename T>
-__device__ __forceinline__ void cswap(cx<T> &a, cx<T> &b, bool hi)
-{
-    constexpr int NWD = (int)sizeof(cx<T>) / 4;
-    unsigned wa[NWD], wb[NWD];
-    __builtin_memcpy(wa, &a, sizeof(a));
-    __builtin_memcpy(wb, &b, sizeof(b));
-#pragma unroll
-    for (int i = 0; i < NWD; ++i) xswap<B>(wa[i], wb[i], hi);
-    __builtin_memcpy(&a, wa, sizeof(a));
-    __builtin_memcpy(&b, wb, sizeof(b));
-}
-
-// slot bits 0 and 1 <-> lane bits BL and BL + 1
-template <int BL, typename T>
-__device__ __forceinline__ void digit_swap(cx<T> (&v)[4], unsigned lane)
-{
-    const bool h0 = (lane >> BL) & 1u, h1 = (lane >> (BL + 1)) & 1u;
-    cswap<BL>(v[0], v[1], h0);
-    cswap<BL>(v[2], v[3], h0);
-    cswap<BL + 1>(v[0], v[2], h1);
-    cswap<BL + 1>(v[1], v[3], h1);
-}
-
-// radix-4 butterfly over the slots: output d in slot d
-template <bool INV, typename T>
-__device__ __forceinline__ void radix4_slots(cx<T> (&v)[4])
-{
-    const cx<T> a = add(v[0], v[2]), b = sub(v[0], v[2]), c = add(v[1], v[3]), d = sub(v[1], v[3]);
-    const cx<T> jd = INV ? cx<T>{-d.im, d.re} : cx<T>{d.im, -d.re};   // (+-i) d
-    v[0] = add(a, c);
-    v[2] = sub(a, c);
-    v[1] = add(b, jd);
-    v[3] = sub(b, jd);
-}
-
-// Stage twiddles of this lane, t[3 g + d - 1] for stage g and digit d = 1..3:
-// forward W_256^{l d}, W_64^{(l mod 16) d}, W_16^{(l mod 4) d}; inverse the
-// conjugates of W_256^{rev(l) d}, W_64^{(l/16 + 4 ((l/4) mod 4)) d},
-// W_16^{(l/16) d}.  `tw` holds W_{2^twlog}^j (twlog >= 8).
-template <bool INV, typename T>
-__device__ __forceinline__ void lane_twiddles(cx<T> *t, const cx<T> *__restrict__ tw, int twlog, unsigned lane)
-{
-    const unsigned sh = (unsigned)(twlog - 8);
-    const unsigned e0 = INV ? ws_out_lane<LaneFFT<T>>(lane) : lane;
-    const unsigned e1 = INV ? (lane >> 4) + 4u * ((lane >> 2) & 3u) : (lane & 15u);
-    const unsigned e2 = INV ? (lane >> 4) : (lane & 3u);
-#pragma unroll
-    for (unsigned d = 1; d < 4; ++d) {
-        t[d - 1] = tw[((e0 * d) & 255u) << sh];
-        t[2 + d] = tw[((4u * e1 * d) & 255u) << sh];
-        t[5 + d] = tw[((16u * e2 * d) & 255u) << sh];
-    }
-    if (INV) {
-#pragma unroll
-        for (int i = 0; i < 9; ++i) t[i] = conjg(t[i]);
-    }
-}
-
-template <typename T>
-__device__ __forceinline__ void lane_twiddle_mul(cx<T> (&v)[4], const cx<T> *t, int g)
-{
-#pragma unroll
-    for (int d = 1; d < 4; ++d) v[d] = mul(v[d], t[3 * g + d - 1]);
-}
-
-template <bool INV, typename T>
-__device__ __forceinline__ void lane_fft(cx<T> (&v)[4], unsigned lane, const cx<T> *t)
-{
-    radix4_slots<INV>(v);
-    lane_twiddle_mul(v, t, 0);
-    if constexpr (INV) digit_swap<0>(v, lane);
-    else digit_swap<4>(v, lane);
-    radix4_slots<INV>(v);
-    lane_twiddle_mul(v, t, 1);
-    digit_swap<2>(v, lane);
-    radix4_slots<INV>(v);
-    lane_twiddle_mul(v, t, 2);
-    if constexpr (INV) digit_swap<4>(v, lane);
-    else digit_swap<0>(v, lane);
-    radix4_slots<INV>(v);
-}
-
 // The wave transform of the wave split: in registers for four points a lane,
 // else the LDS-exchange block transform (xch, twp: its exchange array and
 // stage table; ltw: the in-register transform's lane twiddles).
@@ -632,13 +475,25 @@ __device__ __forceinline__ void ws_fft(cx<T> (&v)[PPT], T *xch, unsigned lane, c
     else F::template run<INV>(v, xch, nullptr, lane, twp, twlog);
 }
 
-template <typename T, int N>
+#ifndef GF_WS_SH_WAVES
+#define GF_WS_SH_WAVES 3
+#endif
+// Layout and launch shape of the wave-split passes.  Unshared (SH false):
+// each column group of a workgroup owns one (column unit, model) item with
+// its own spectrum buffers.  Shared (SH): the groups of a workgroup (256
+// threads, or 512 for columns of four or more waves) are models of one
+// column unit, staging its spectrum rows once into one set of buffers, which
+// leaves LDS for more resident waves when a batch of models shares the
+// geometry (up to GF_WS_SH_WAVES a SIMD: the accumulators of six spectra
+// take most of the registers of three).
+template <typename T, int N, bool SH = false>
 struct WsCfg {
     static constexpr int PPT = ws_ppt<T, N>();
     static constexpr int L = 64 * PPT;                                // one wave's transform length
     static constexpr int NW = N / L;                                  // waves per column
-    static constexpr int G = NW >= 4 ? 1 : 4 / NW;                    // columns per workgroup
     static constexpr int GT = 64 * NW;                                // threads per column
+    static constexpr int G = SH ? (GT <= 128 ? 256 / GT : (GT >= 512 ? 1 : 512 / GT))
+                                : (NW >= 4 ? 1 : 4 / NW);             // columns per workgroup
     static constexpr int THREADS = G * GT;
     // four points a lane: the in-register transform; eight: LDS exchanges
     static constexpr bool LANE = PPT == 4;
@@ -649,28 +504,60 @@ struct WsCfg {
     static constexpr int TWW = up(2 * FFT::stw_entries());            // stage twiddles, shared
     static constexpr int QP = up(N / 2 + 1);                          // padded spectrum row
     static constexpr int CW = N;                                      // one column buffer (N/2 complex)
+    static constexpr int GW = 2 * CW + NW * XW;                       // a group's columns and exchange arrays
     // T words per column: nbuf spectrum buffers, two column buffers and the
-    // waves' exchange arrays.  At the end, the first 2N words (re, im of N
-    // values) hold the combination of the waves' inverse transforms.
-    static constexpr int words_with(int nbuf, int cmax) { return nbuf * cmax * QP + 2 * CW + NW * XW; }
+    // waves' exchange arrays (the spectrum buffers once per workgroup when
+    // shared).  At the end, 2N words of the group (re, im of N values) hold
+    // the combination of the waves' inverse transforms: the start of its
+    // area (unshared) or its column buffers (shared).
+    static constexpr int words_with(int nbuf, int cmax) { return nbuf * cmax * QP + GW; }
     static constexpr size_t bytes_with(int nbuf, int cmax)
     {
-        return ((size_t)G * words_with(nbuf, cmax) + TWW) * sizeof(T);
+        return SH ? ((size_t)nbuf * cmax * QP + (size_t)G * GW + TWW) * sizeof(T)
+                  : ((size_t)G * words_with(nbuf, cmax) + TWW) * sizeof(T);
     }
+    static constexpr int fit(size_t bytes) { return (int)(163840 / bytes); }
     // Two spectrum buffers (the next layer's rows stream in while this layer
-    // is reduced) unless only one fits in the 160 KB of LDS of a CU: FP64 at
-    // length 4096 holds three spectra with one buffer, one with two.  With
+    // is reduced) unless only one fits in the 160 KB of LDS of a CU (FP64 at
+    // length 4096 holds three spectra with one buffer, one with two), or,
+    // shared, unless one buffer fits more workgroups per CU (up to two).  With
     // one buffer the next layer's rows stream in while the next column is
     // transformed.
-    static constexpr bool single_spec(int cmax) { return bytes_with(2, cmax) > 163840 && bytes_with(1, cmax) <= 163840; }
+    static constexpr int WPW = THREADS >= 256 ? THREADS / 256 : 1;   // waves per SIMD of one workgroup
+    static constexpr int WG_CAP = SH ? (GF_WS_SH_WAVES / WPW > 0 ? GF_WS_SH_WAVES / WPW : 1) : 64;
+    static constexpr int fit_capped(size_t bytes) { return fit(bytes) < WG_CAP ? fit(bytes) : WG_CAP; }
+    static constexpr bool single_spec(int cmax)
+    {
+        if (SH) return fit_capped(bytes_with(2, cmax)) < fit_capped(bytes_with(1, cmax));
+        return bytes_with(2, cmax) > 163840 && bytes_with(1, cmax) <= 163840;
+    }
     static constexpr int spec_bufs(int cmax) { return single_spec(cmax) ? 1 : 2; }
-    static constexpr int group_words(int cmax) { return words_with(spec_bufs(cmax), cmax); }
+    static constexpr int group_words(int cmax) { return SH ? GW : words_with(spec_bufs(cmax), cmax); }
     static constexpr size_t lds_bytes(int cmax) { return bytes_with(spec_bufs(cmax), cmax); }
-    // register target: waves per SIMD of the workgroups that fit in 160 KB of LDS
-    static constexpr int WG_PER_CU = (int)(163840 / lds_bytes(6)) > 0 ? (int)(163840 / lds_bytes(6)) : 1;
-    static constexpr int WAVES_PER_EU = (THREADS >= 256 ? THREADS / 256 : 1) * WG_PER_CU;
+    // register target: waves per SIMD of the workgroups that fit in 160 KB of
+    // LDS (shared: capped as above)
+    static constexpr int WG_PER_CU = fit_capped(lds_bytes(6)) > 0 ? fit_capped(lds_bytes(6)) : 1;
+    static constexpr int WAVES_PER_EU = WPW * WG_PER_CU;
     static_assert(N % L == 0 && NW >= 1 && NW <= 8, "wave split needs N = NW * L with NW in 1..8");
 };
+
+// Whether the shared layout serves a batch of B models at length N: it
+// exists where a workgroup holds two or more columns, and runs when the
+// models fill its groups (few idle groups).
+template <typename T, int N>
+constexpr bool ws_shared_exists()
+{
+    if constexpr (use_ws<N>())
+        return WsCfg<T, N, true>::G >= 2 && WsCfg<T, N, true>::WAVES_PER_EU > WsCfg<T, N, false>::WAVES_PER_EU;
+    else
+        return false;
+}
+template <typename T, int N>
+inline bool ws_shared_for(int B)
+{
+    constexpr int G = WsCfg<T, N, true>::G;
+    return ws_shared_exists<T, N>() && B >= 2 && (B % G == 0 || B >= 2 * G);
+}
 
 // Position of frequency ky in [0, N/2] within a resident spectrum row:
 // residue blocks r = ky mod NW (block 0 holds N/(2 NW) + 1 values, the
@@ -947,7 +834,7 @@ struct WsItem {
     bool active, nyq;
 };
 
-template <int GT, int G>
+template <int GT, int G, bool SH = false>
 __device__ __forceinline__ WsItem ws_item(unsigned g, int M, int B, int nz, int lps, int nblk_ny, int Sny,
                                           int lps_ny, int nblk_main)
 {
@@ -971,11 +858,20 @@ __device__ __forceinline__ WsItem ws_item(unsigned g, int M, int B, int nz, int 
     } else {
         const unsigned bm = bx - (unsigned)nblk_ny;
         it.split = (int)(bm / (unsigned)nblk_main);
-        const unsigned gi = (bm % (unsigned)nblk_main) * G + g;
-        it.active = gi < (unsigned)M * (unsigned)B;
-        const unsigned gc = it.active ? gi : 0u;
-        it.uv = gc / (unsigned)B;
-        it.b = gc % (unsigned)B;
+        if constexpr (SH) {
+            // the groups are models of one unit: nblk_main = M * ceil(B / G)
+            const unsigned nbb = ((unsigned)B + G - 1) / G, r = bm % (unsigned)nblk_main;
+            const unsigned bb = (r % nbb) * G + g;
+            it.active = bb < (unsigned)B;
+            it.uv = r / nbb;
+            it.b = it.active ? bb : 0u;
+        } else {
+            const unsigned gi = (bm % (unsigned)nblk_main) * G + g;
+            it.active = gi < (unsigned)M * (unsigned)B;
+            const unsigned gc = it.active ? gi : 0u;
+            it.uv = gc / (unsigned)B;
+            it.b = gc % (unsigned)B;
+        }
         it.u = it.uv;
         it.part = it.uv == 0 ? 1 : 0;
         it.nyq = false;
@@ -990,15 +886,15 @@ __device__ __forceinline__ WsItem ws_item(unsigned g, int M, int B, int nz, int 
     return it;
 }
 
-template <typename T, int N, int CMAX, int KIND>
-__global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
-    __attribute__((amdgpu_waves_per_eu(WsCfg<T, N>::WAVES_PER_EU)))
+template <typename T, int N, int CMAX, int KIND, bool SH>
+__global__ void __launch_bounds__((WsCfg<T, N, SH>::THREADS))
+    __attribute__((amdgpu_waves_per_eu(WsCfg<T, N, SH>::WAVES_PER_EU)))
     col_forward_ws_kernel(const cx<T> *__restrict__ R, const T *__restrict__ spec, cx<T> *__restrict__ D,
                           T *__restrict__ Dny, int B, int nz, int M, int ny, int ldc, int Cs, int Ct, int lps,
                           int nblk_ny, int Sny, int lps_ny, int nblk_main, unsigned imag_mask,
                           unsigned yodd_mask, const cx<T> *__restrict__ tw, int twlog)
 {
-    using C = WsCfg<T, N>;
+    using C = WsCfg<T, N, SH>;
     using F = typename C::FFT;
     constexpr int PPT = C::PPT, L = C::L, NW = C::NW, G = C::G, GT = C::GT, QP = C::QP;
     const unsigned im_m = KIND >= 0 ? (unsigned)(KIND & 0xFF) : imag_mask;
@@ -1011,11 +907,15 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     const unsigned g = wv / NW, w = wv % NW;
     const unsigned tg = threadIdx.x - g * GT;
     constexpr int NB = C::spec_bufs(CMAX);
+    // spectrum rows are staged by the group (unshared) or by the workgroup (shared)
+    constexpr int ST = SH ? C::THREADS : GT;
+    const unsigned ts = SH ? threadIdx.x : tg;
     T *twq = lds;
-    T *gb = lds + C::TWW + (size_t)g * C::group_words(CMAX);
-    T *sbuf = gb;                                                        // NB x CMAX x QP
-    cx<T> *cbuf = reinterpret_cast<cx<T> *>(gb + NB * CMAX * QP);        // 2 x N/2 complex
-    T *xch = gb + NB * CMAX * QP + 2 * C::CW + w * C::XW;
+    T *gb = lds + C::TWW + (SH ? NB * CMAX * QP : 0) + (size_t)g * C::group_words(CMAX);
+    T *sbuf = SH ? lds + C::TWW : gb;                                    // NB x CMAX x QP
+    T *cw = SH ? gb : gb + NB * CMAX * QP;
+    cx<T> *cbuf = reinterpret_cast<cx<T> *>(cw);                         // 2 x N/2 complex
+    T *xch = cw + 2 * C::CW + w * C::XW;
     const cx<T> *twp = reinterpret_cast<const cx<T> *>(twq);
     F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
     for (unsigned i = (unsigned)ny + tg; i < (unsigned)(N / 2); i += GT) {
@@ -1037,7 +937,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
-    const WsItem un = ws_item<GT, G>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
+    const WsItem un = ws_item<GT, G, SH>(g, M, B, nz, lps, nblk_ny, Sny, lps_ny, nblk_main);
     const unsigned row = spec_row(un.uv, (unsigned)M);
     const size_t layer_vals = (size_t)(M + 1) * Cs * QP;
     const int n0 = un.n0;
@@ -1051,8 +951,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 
     cx<T> tail{T(0), T(0)};
     auto stage_spec = [&](int n, int buf) {
-        stage_rows<T, GT, true>(spec + (size_t)n * layer_vals + (size_t)row * Cs * QP, sbuf + buf * CMAX * QP,
-                                (unsigned)Cs * QP, tg);
+        stage_rows<T, ST, true>(spec + (size_t)n * layer_vals + (size_t)row * Cs * QP, sbuf + buf * CMAX * QP,
+                                (unsigned)Cs * QP, ts);
     };
     auto stage_col = [&](int n, int buf) {
         stage_column<T, GT>(column(R, (size_t)un.b * nz + n, M, un.u, ldc), cbuf + buf * (N / 2), ny, tg, tail);
@@ -1097,9 +997,9 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
         }
     }
 
-    // every wave is past its last reads of the staged buffers: the first 2N
-    // words of the group's area take the waves' inverse transforms
-    T *cre = gb;
+    // every wave is past its last reads of the staged buffers: 2N words of
+    // the group's area take the waves' inverse transforms
+    T *cre = SH ? cw : gb;
     if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
 #pragma unroll
     for (int c = 0; c < CMAX; ++c) {
@@ -1948,22 +1848,37 @@ __global__ void __launch_bounds__((ColCfg<double, N>::THREADS))
     }
 }
 
+template <typename T, int N, int CMAX, int KIND, bool SH>
+static int run_fwd_ws(const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc, int Cs,
+                      int Ct, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
+                      const void *tw, int twlog, hipStream_t st)
+{
+    using C = WsCfg<T, N, SH>;
+    const long nbb = (B + C::G - 1) / C::G;
+    const long nblk_main = SH ? (long)M * nbb : ((long)M * B + C::G - 1) / C::G;
+    const long nblk_ny = (long)nq.Sny * nbb;
+    const size_t lds = C::lds_bytes(CMAX);
+    if (lds > lds_limit()) return -3;
+    if (nq.Sny < 1 || nq.lps_ny < 1 || !nq.Dny) return -2;
+    hipLaunchKernelGGL((col_forward_ws_kernel<T, N, CMAX, KIND, SH>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
+                       dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
+                       (T *)nq.Dny, B, nz, M, ny, ldc, Cs, Ct, lps, (int)nblk_ny, nq.Sny, nq.lps_ny,
+                       (int)nblk_main, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <typename T, int N, int CMAX, int KIND>
 static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int M, int ny, int ldc, int Cs,
                    int Ct, int nsplit, int lps, const NyqSplit &nq, unsigned imag_mask, unsigned yodd_mask,
                    const void *tw, int twlog, hipStream_t st)
 {
     if constexpr (use_ws<N>()) {
-        using C = WsCfg<T, N>;
-        const long nblk_main = ((long)M * B + C::G - 1) / C::G;
-        const long nblk_ny = (long)nq.Sny * ((B + C::G - 1) / C::G);
-        const size_t lds = C::lds_bytes(CMAX);
-        if (lds > lds_limit()) return -3;
-        if (nq.Sny < 1 || nq.lps_ny < 1 || !nq.Dny) return -2;
-        hipLaunchKernelGGL((col_forward_ws_kernel<T, N, CMAX, KIND>), dim3((unsigned)(nblk_ny + nsplit * nblk_main)),
-                           dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
-                           (T *)nq.Dny, B, nz, M, ny, ldc, Cs, Ct, lps, (int)nblk_ny, nq.Sny, nq.lps_ny,
-                           (int)nblk_main, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+        if constexpr (ws_shared_exists<T, N>())
+            if (ws_shared_for<T, N>(B))
+                return run_fwd_ws<T, N, CMAX, KIND, true>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq,
+                                                          imag_mask, yodd_mask, tw, twlog, st);
+        return run_fwd_ws<T, N, CMAX, KIND, false>(R, spec, D, B, nz, M, ny, ldc, Cs, Ct, nsplit, lps, nq,
+                                                   imag_mask, yodd_mask, tw, twlog, st);
     } else {
         using C = ColCfg<T, N>;
         const long groups = (long)(M + 1) * B;
@@ -1973,8 +1888,8 @@ static int run_fwd(const void *R, const void *spec, void *D, int B, int nz, int 
         hipLaunchKernelGGL((col_forward_kernel<T, N, CMAX, KIND>), dim3((unsigned)nblk, (unsigned)nsplit),
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)D,
                            B, nz, M, ny, ldc, Cs, Ct, lps, imag_mask, yodd_mask, (const cx<T> *)tw, twlog);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T, int N, int CMAX, int KIND>
@@ -1983,6 +1898,9 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
                    const void *tw, int twlog, hipStream_t st)
 {
     if constexpr (use_ws<N>()) {
+        // the adjoint keeps one item per group: its Cs transformed residual
+        // columns stay in registers across the layers, which leaves no room
+        // for the extra resident waves of the shared layout
         using C = WsCfg<T, N>;
         const long nblk_main = ((long)M * B + C::G - 1) / C::G;
         const long nblk_ny = (long)nq.Sny * ((B + C::G - 1) / C::G);
@@ -1993,6 +1911,7 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec, (cx<T> *)Gout, B, nz,
                            M, ny, ldc, Cs, Ct, lps, (int)nblk_ny, nq.Sny, nq.lps_ny, (int)nblk_main, imag_mask,
                            yodd_mask, (const cx<T> *)tw, twlog);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
     } else {
         using C = ColCfg<T, N>;
         const long groups = (long)(M + 1) * B;
@@ -2003,8 +1922,8 @@ static int run_adj(const void *R, const void *spec, void *Gout, int B, int nz, i
                            dim3(C::THREADS), lds, st, (const cx<T> *)R, (const T *)spec,
                            (cx<T> *)Gout, B, nz, M, ny, ldc, Cs, Ct, lps, imag_mask, yodd_mask,
                            (const cx<T> *)tw, twlog);
+        return hipGetLastError() == hipSuccess ? 0 : -1;
     }
-    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 template <typename T, int N>
@@ -2274,13 +2193,13 @@ static int capacity_of(int Cs)
     if constexpr (use_ws<N>()) {
         using C = WsCfg<T, N>;
         if (Cs <= 1)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 1, -1>, C::THREADS,
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 1, -1, false>, C::THREADS,
                                                              C::lds_bytes(1));
         else if (Cs <= 3)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 3, -1>, C::THREADS,
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 3, -1, false>, C::THREADS,
                                                              C::lds_bytes(3));
         else
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 6, -1>, C::THREADS,
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, col_forward_ws_kernel<T, N, 6, -1, false>, C::THREADS,
                                                              C::lds_bytes(6));
     } else {
         using C = ColCfg<T, N>;

@@ -219,6 +219,42 @@ def test_wave_split_batches(gf, orc, nx, ny, prec, tol):
     p.close()
 
 
+# batches of models run the column passes with the groups of a workgroup on
+# one column unit, its spectrum rows staged once (column lengths 256 and 512
+# in both precisions, 1024 in FP32): 4 models fill the groups, 9 leave some
+# idle; 21 layers (Nyquist chunks, the last one short)
+@pytest.mark.parametrize("prec,tol", [("f64", TOL64), ("f32", TOL32)])
+@pytest.mark.parametrize("nx,ny", [(90, 110), (50, 200), (64, 400)])
+@pytest.mark.parametrize("nb", [4, 9])
+def test_shared_spectrum_batches(gf, orc, nx, ny, nb, prec, tol):
+    g = Geometry(nx, ny, 21, 20.0, 25.0, 15.0, 7.0)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rho = np.stack([tiny_density(g.nx, g.ny, g.nz, seed=40 + s, block=None) for s in range(nb)])
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, ALL9, prec)
+    note("shared spectra %dx%dx%d %s: batch of %d" % (nx, ny, g.nz, prec, nb))
+    both = p.forward(torch.from_numpy(rho).to("cuda", dt)).double().cpu().numpy()
+    for b in (0, nb // 2, nb - 1):
+        one = p.forward(torch.from_numpy(rho[b]).to("cuda", dt)).double().cpu().numpy()
+        assert np.array_equal(both[b], one), b
+    st = np.array([(0, 0), (nx - 1, ny - 1), (nx // 2, ny // 3), (nx // 5, (3 * ny) // 4)])
+    bl = nb - 1
+    want = orc.forward(g, rho[bl], st)
+    for c in range(NC):
+        e = rel(both[bl][c][st[:, 1], st[:, 0]], want[:, c])
+        assert e <= tol, (NAMES[c], e)
+    rng = np.random.default_rng(7 * nx + ny + nb)
+    r = rng.uniform(-1.0, 1.0, size=(nb, NC, ny, nx))
+    gt = p.adjoint(torch.from_numpy(r).to("cuda", dt)).double().cpu().numpy()
+    for b in (0, nb - 1):
+        one = p.adjoint(torch.from_numpy(r[b]).to("cuda", dt)).double().cpu().numpy()
+        assert np.array_equal(gt[b], one), b
+    lhs = float(np.sum(both * r))
+    rhs = float(np.sum(rho * gt))
+    dtol = 1e-13 if prec == "f64" else 1e-6
+    assert abs(lhs - rhs) <= dtol * np.linalg.norm(both) * np.linalg.norm(r), (lhs, rhs)
+    p.close()
+
+
 def test_deterministic(gf):
     g = Geometry(40, 30, 12, 20.0, 20.0, 20.0, 10.0)
     rho = tiny_density(g.nx, g.ny, g.nz, seed=9, block=None)
