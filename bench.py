@@ -46,7 +46,7 @@ import numpy as np  # noqa: E402
 METRIC = "effective N_d·N_m kernel-evals/s at 1024²×100 6-comp; p50/p99 served latency"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_colpass_paper_scale.json")
-KERNEL_SOURCES = ["colpass.hip", "gf_fft.h"]
+KERNEL_SOURCES = ["colpass.hip", "gf_fft.h", "gf_lane.h"]
 
 
 def log(msg):
@@ -539,9 +539,9 @@ def main():
 
         # the equal-dimension survey: as many observation levels as layers
         # (stations on 100 planes 20 m apart above the model), six
-        # components; each level is a column pass over its window of the
-        # 199 resident layer spectra
-        # gz alone runs six levels per column pass
+        # components and gz alone; the plan picks how its levels run
+        # (reported as level_path: 3 the direct Toeplitz product in depth,
+        # 4 the same through the transform in depth)
         lev = {"levels": g.nz, "workload": "equal-dimension survey, %dx%dx%d model, %d observation levels, "
                                            "batch 1" % (g.nx, g.ny, g.nz, g.nz)}
         for name, mask in (("all6", gf.ALL6), ("gz", gf.GZ)):

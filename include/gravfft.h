@@ -112,8 +112,10 @@ typedef struct {
                               per level; 2 column passes of several levels;
                               3 the Toeplitz product in depth (the column
                               transforms once, the depth products of every
-                              level per frequency, the inverse transforms once) */
-    int level_chunk;       /* levels per chunk of path 3 (0 otherwise)           */
+                              level per frequency, the inverse transforms once);
+                              4 path 3 with the depth products through a
+                              transform in depth of length 256 (FP64)        */
+    int level_chunk;       /* levels per chunk of paths 3 and 4 (0 otherwise)    */
 } gf_plan_info_t;
 
 /*
@@ -270,9 +272,11 @@ gf_status gf_debug_spectrum(const gf_plan *plan, unsigned component, int n, doub
 
 /*
  * Test hook: how plans of several observation levels created afterwards run
- * them.  mode 0: the path whose estimated traffic is lowest (the default);
+ * them.  mode 0: the path whose estimated cost is lowest (the default);
  * 1: column passes (one or several levels each); 2: the Toeplitz product in
- * depth, where the transform length allows it (column lengths >= 256).
+ * depth, where the transform length allows it (column lengths >= 256);
+ * 3: the same with the depth products through the transform in depth
+ * (FP64 plans where also nz + levels - 1 <= 256; otherwise as 2).
  * max_chunk > 0 caps the levels per chunk of the Toeplitz path (0: its
  * default, 32 GiB of chunk buffers per model).  Process-wide.  GF_EINVAL for
  * other values.

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgravfft.so")
-SOURCES = ["plan.hip", "rows.hip", "colpass.hip", "kgen.hip"]
+SOURCES = ["plan.hip", "rows.hip", "colpass.hip", "kgen.hip", "levelz.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

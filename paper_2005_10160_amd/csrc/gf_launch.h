@@ -131,6 +131,23 @@ int launch_levels_forward(bool fp64, int py, const void *X, const void *spec, vo
 int launch_levels_adjoint(bool fp64, int py, const void *Rh, const void *spec, void *Gh, int B, int nz, int nlev, int M,
                           int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, bool accumulate, hipStream_t st);
 
+// Observation levels through a transform in depth of length 256 (FP64
+// plans): plan-time Kz[row][c][j][QP] (complex, j <= 128) of a group's window
+// of nwin <= 256 spectral layers, and the forward / adjoint of a chunk of
+// levels [t0, t0 + tc) of nt, in the layouts of launch_levels_forward /
+// launch_levels_adjoint (Kz of the group instead of its spectra window;
+// t0 absolute).
+bool levelz_supported(int nwin);
+size_t levelz_values(int U1, int Cs, int QP);
+int launch_levelz_kgen(const void *spec, void *kz, int nwin, int U1, int Cs, int QP, const void *tw64, int twlog,
+                       hipStream_t st);
+int launch_levelz_forward(const void *X, const void *kz, void *Dh, int B, int nz, int t0, int tc, int nt, int U1,
+                          int QP, int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, const void *tw, int twlog,
+                          hipStream_t st);
+int launch_levelz_adjoint(const void *Rh, const void *kz, void *Gh, int B, int nz, int t0, int tc, int nt, int U1,
+                          int QP, int Cs, int Ct, unsigned imag_mask, unsigned yodd_mask, bool accumulate,
+                          const void *tw, int twlog, hipStream_t st);
+
 // Plan time: column FFT of the row-transformed kernel fields and extraction
 // of the quarter-plane spectrum into spec[Cs][nz][M+1][py/2+1] (float or double).
 int launch_col_kgen(bool out_fp64, int py, const void *Rk, void *spec, int nl, int n0, int Cs,

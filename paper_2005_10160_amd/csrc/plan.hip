@@ -102,8 +102,9 @@ size_t g_live_bytes = 0;
 long g_fail_countdown = 0;
 
 // Test hook (gf_debug_level_path): how plans created afterwards run their
-// observation levels (0: by their byte estimate, 1: column passes, 2: the
-// Toeplitz product), and a cap on the Toeplitz path's levels per chunk.
+// observation levels (0: by their cost estimates, 1: column passes, 2: the
+// Toeplitz product, 3: the Toeplitz product through the transform in depth),
+// and a cap on the Toeplitz path's levels per chunk.
 std::mutex g_level_mu;
 int g_level_path = 0, g_level_chunk = 0;
 
@@ -233,6 +234,27 @@ struct gf_plan {
     }
     bool toep = false;              // decided at creation
     int toep_tc = 1;
+    // the Toeplitz path's depth products through the transform in depth
+    // (decided at creation), with its plan-time values Kz, per group
+    // [U][Cs][129][QP] complex, groups one after the other
+    bool zdepth = false;
+    void *kz = nullptr;
+    size_t kz_bytes = 0;
+    char *kz_group(int g) const { return (char *)kz + 2 * elem() * gf::levelz_values(U, grp_c0[g], QP); }
+    // Depth products of one component over all (row, half, position)
+    // sequences of the 1024^2 x 100, 100-level survey in FP64, measured: the
+    // direct Toeplitz product 3.8 ms (it scales with nz * nt), the transform
+    // in depth 4.0 ms for the inputs' transform and staging plus 1.6 ms per
+    // component (independent of nz and nt up to nz + nt - 1 = 256).  FP32
+    // keeps the direct product: the transform in depth rounds relative to the
+    // whole depth sequence, which leaves levels far above the model with
+    // about 1e-5 of their own size in FP32 (1e-11 in FP64).
+    bool depth_transform_cheaper() const
+    {
+        const double direct = 3.8e-4 * n_spec * nz * nt;
+        const double zt = 4.0 + 1.6 * n_spec;
+        return zt < direct;
+    }
     bool levels_toeplitz() const { return toep; }
     int toep_chunk() const { return toep_tc; }
     unsigned grp_bits(unsigned m, int g) const { return (m >> grp_c0[g]) & ((1u << grp_cs[g]) - 1u); }
@@ -423,6 +445,7 @@ void free_plan(gf_plan *p)
         for (int i = 0; i < 4; ++i)
             if (p->ev[o][i]) (void)hipEventDestroy(p->ev[o][i]);
     dev_free(p->spec);
+    dev_free(p->kz);
     dev_free(p->tw);
     if (p->tw64 != p->tw) dev_free(p->tw64);
     dev_free(p->iws);
@@ -484,7 +507,7 @@ const char *gf_last_error(void) { return g_err.c_str(); }
 
 gf_status gf_debug_level_path(int mode, int max_chunk)
 {
-    if (mode < 0 || mode > 2 || max_chunk < 0) return fail(GF_EINVAL, "bad level path %d / chunk %d", mode, max_chunk);
+    if (mode < 0 || mode > 3 || max_chunk < 0) return fail(GF_EINVAL, "bad level path %d / chunk %d", mode, max_chunk);
     std::lock_guard<std::mutex> lk(g_level_mu);
     g_level_path = mode;
     g_level_chunk = max_chunk;
@@ -580,7 +603,9 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     {
         std::lock_guard<std::mutex> lk(g_level_mu);
         if (nt > 1 && gf::col_spectra_supported(p->py))
-            p->toep = g_level_path == 2 || (g_level_path == 0 && p->toeplitz_cheaper());
+            p->toep = g_level_path == 2 || g_level_path == 3 || (g_level_path == 0 && p->toeplitz_cheaper());
+        p->zdepth = p->toep && p->fp64() && gf::levelz_supported(p->nzs) && p->twlog >= 8 &&
+                    (g_level_path == 3 || (g_level_path == 0 && p->depth_transform_cheaper()));
         p->toep_tc = p->toep_chunk_default();
         if (g_level_chunk > 0) p->toep_tc = std::min(p->toep_tc, g_level_chunk);
     }
@@ -663,6 +688,23 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     if ((s = build_spectra(p, st)) != GF_OK) {
         free_plan(p);
         return s;
+    }
+    if (p->zdepth) {
+        p->kz_bytes = 2 * p->elem() * gf::levelz_values(p->U, p->n_spec, p->QP);
+        if ((s = hip_check(dev_malloc((void **)&p->kz, p->kz_bytes), "depth-transformed spectra")) != GF_OK) {
+            free_plan(p);
+            return s;
+        }
+        for (int gr = 0; gr < p->ngrp; ++gr)
+            if (gf::launch_levelz_kgen(p->spec_group(gr), p->kz_group(gr), p->nzs, p->U, p->grp_cs[gr],
+                                       p->QP, p->tw64, p->twlog, st) != 0) {
+                free_plan(p);
+                return fail(GF_EDEVICE, "depth transform launch failed");
+            }
+        if ((s = hip_check(hipStreamSynchronize(st), "plan synchronise")) != GF_OK) {
+            free_plan(p);
+            return s;
+        }
     }
     if (max_batch > 0) {
         p->iws_bytes = std::max(p->ws_bytes(GF_OP_FORWARD, max_batch), p->ws_bytes(GF_OP_ADJOINT, max_batch));
@@ -752,15 +794,15 @@ gf_status gf_plan_get_info(const gf_plan *p, gf_plan_info_t *info)
     info->spec_mask = p->spec_mask;
     info->precision = p->prec;
     info->max_batch = p->max_batch;
-    info->spectra_bytes = p->spec_bytes;
+    info->spectra_bytes = p->spec_bytes + p->kz_bytes;
     info->internal_workspace_bytes = p->iws_bytes;
     info->plan_ms = p->plan_ms;
-    info->level_path = p->nt < 2 ? 0 : (p->toep ? 3 : (p->levels_blocked() ? 2 : 1));
+    info->level_path = p->nt < 2 ? 0 : (p->toep ? (p->zdepth ? 4 : 3) : (p->levels_blocked() ? 2 : 1));
     info->level_chunk = p->toep ? p->toep_tc : 0;
     return GF_OK;
 }
 
-size_t gf_plan_bytes(const gf_plan *p) { return p ? p->spec_bytes : 0; }
+size_t gf_plan_bytes(const gf_plan *p) { return p ? p->spec_bytes + p->kz_bytes : 0; }
 
 gf_status gf_workspace_bytes(const gf_plan *p, int op, int batch, size_t *bytes)
 {
@@ -826,12 +868,19 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
         const gf::NyqSplit none{nullptr, 0, 0};
         for (int t0 = 0; t0 < p->nt; t0 += tcm) {
             const int tc = std::min(tcm, p->nt - t0);
-            for (int gr = 0; gr < p->ngrp; ++gr)
-                if (gf::launch_levels_forward(p->fp64(), p->py, X, p->spec_window(gr, t0),
-                                              Dh + p->sp_slab_bytes() * (size_t)p->grp_c0[gr], batch, p->nz, tc, p->M,
-                                              p->grp_cs[gr], p->n_spec, p->grp_bits(p->imag_mask, gr),
-                                              p->grp_bits(p->yodd_mask, gr), st) != 0)
-                    return fail(GF_EDEVICE, "depth product launch: %s", hipGetErrorString(hipGetLastError()));
+            for (int gr = 0; gr < p->ngrp; ++gr) {
+                char *Dg = Dh + p->sp_slab_bytes() * (size_t)p->grp_c0[gr];
+                const int e = p->zdepth
+                                  ? gf::launch_levelz_forward(X, p->kz_group(gr), Dg, batch, p->nz, t0, tc,
+                                                              p->nt, p->U, p->QP, p->grp_cs[gr], p->n_spec,
+                                                              p->grp_bits(p->imag_mask, gr),
+                                                              p->grp_bits(p->yodd_mask, gr), p->tw, p->twlog, st)
+                                  : gf::launch_levels_forward(p->fp64(), p->py, X, p->spec_window(gr, t0), Dg, batch,
+                                                              p->nz, tc, p->M, p->grp_cs[gr], p->n_spec,
+                                                              p->grp_bits(p->imag_mask, gr),
+                                                              p->grp_bits(p->yodd_mask, gr), st);
+                if (e != 0) return fail(GF_EDEVICE, "depth product launch: %s", hipGetErrorString(hipGetLastError()));
+            }
             const int slots = tc * p->n_spec;
             if (gf::launch_col_inverse(p->fp64(), p->py, Dh, Dc, batch, slots, p->M, p->ny, p->ldc, p->tw, p->twlog,
                                        st) != 0)
@@ -975,12 +1024,20 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
             if (gf::launch_col_spectra(p->fp64(), p->py, Rl, Xr, batch, slots, p->M, p->ny, p->ldc, p->tw, p->twlog,
                                        st) != 0)
                 return fail(GF_EDEVICE, "column spectra launch: %s", hipGetErrorString(hipGetLastError()));
-            for (int gr = 0; gr < p->ngrp; ++gr)
-                if (gf::launch_levels_adjoint(p->fp64(), p->py, Xr + ss * (size_t)p->grp_c0[gr], p->spec_window(gr, t0),
-                                              Gh, batch, p->nz, tc, p->M, p->grp_cs[gr], p->n_spec,
-                                              p->grp_bits(p->imag_mask, gr), p->grp_bits(p->yodd_mask, gr),
-                                              t0 > 0 || gr > 0, st) != 0)
-                    return fail(GF_EDEVICE, "depth product launch: %s", hipGetErrorString(hipGetLastError()));
+            for (int gr = 0; gr < p->ngrp; ++gr) {
+                const char *Xg = Xr + ss * (size_t)p->grp_c0[gr];
+                const int e = p->zdepth
+                                  ? gf::launch_levelz_adjoint(Xg, p->kz_group(gr), Gh, batch, p->nz, t0, tc,
+                                                              p->nt, p->U, p->QP, p->grp_cs[gr], p->n_spec,
+                                                              p->grp_bits(p->imag_mask, gr),
+                                                              p->grp_bits(p->yodd_mask, gr), t0 > 0 || gr > 0, p->tw,
+                                                              p->twlog, st)
+                                  : gf::launch_levels_adjoint(p->fp64(), p->py, Xg, p->spec_window(gr, t0), Gh, batch,
+                                                              p->nz, tc, p->M, p->grp_cs[gr], p->n_spec,
+                                                              p->grp_bits(p->imag_mask, gr),
+                                                              p->grp_bits(p->yodd_mask, gr), t0 > 0 || gr > 0, st);
+                if (e != 0) return fail(GF_EDEVICE, "depth product launch: %s", hipGetErrorString(hipGetLastError()));
+            }
         }
         if (gf::launch_col_inverse(p->fp64(), p->py, Gh, Gc, batch, p->nz, p->M, p->ny, p->ldc, p->tw, p->twlog, st) != 0)
             return fail(GF_EDEVICE, "inverse column launch: %s", hipGetErrorString(hipGetLastError()));
