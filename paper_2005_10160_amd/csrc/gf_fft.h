@@ -155,11 +155,12 @@ __device__ __forceinline__ cx<T> twiddle(const cx<T> *__restrict__ tw, int twlog
 // imaginary parts are exchanged one after the other (half the LDS, twice the
 // barriers).  Exchange indices are padded per stage (see xpad) to avoid bank
 // conflicts.
-// With WAVESYNC (a group of exactly one wave) the exchanges are ordered by
-// waiting for this wave's own LDS operations instead of a workgroup barrier.
+// With WAVESYNC (a group within one wave: NT dividing 64, groups aligned to
+// waves) the exchanges are ordered by waiting for this wave's own LDS
+// operations instead of a workgroup barrier.
 template <typename T, int N, int NT, int R, bool XSPLIT = false, bool TWS = false, bool WAVESYNC = false>
 struct BlockFFT {
-    static_assert(!WAVESYNC || NT == 64, "wave-local exchange needs one wave per transform");
+    static_assert(!WAVESYNC || (NT <= 64 && 64 % NT == 0), "wave-local exchange needs transforms within one wave");
     __device__ __forceinline__ static void xsync()
     {
         if constexpr (WAVESYNC)

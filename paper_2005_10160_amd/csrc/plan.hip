@@ -236,7 +236,7 @@ struct gf_plan {
     int toep_tc = 1;
     // the Toeplitz path's depth products through the transform in depth
     // (decided at creation), with its plan-time values Kz, per group
-    // [U][Cs][129][QP] complex, groups one after the other
+    // [U][Cs][tile][129][8] complex (positions in tiles of 8), groups one after the other
     bool zdepth = false;
     void *kz = nullptr;
     size_t kz_bytes = 0;
@@ -692,6 +692,11 @@ static gf_status create_plan(int nx, int ny, int nz, int nt, double dx, double d
     if (p->zdepth) {
         p->kz_bytes = 2 * p->elem() * gf::levelz_values(p->U, p->n_spec, p->QP);
         if ((s = hip_check(dev_malloc((void **)&p->kz, p->kz_bytes), "depth-transformed spectra")) != GF_OK) {
+            free_plan(p);
+            return s;
+        }
+        // zero first: the last position tile of each row has padding slots
+        if ((s = hip_check(hipMemsetAsync(p->kz, 0, p->kz_bytes, st), "memset")) != GF_OK) {
             free_plan(p);
             return s;
         }
