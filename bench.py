@@ -88,8 +88,25 @@ def colpass_algorithmic_bytes(p, B):
     return spectra + R + D + Dny, S
 
 
+def settle(fn, seconds=0.3, max_calls=300):
+    """Untimed applies for a fraction of a second before the warm-up steps:
+    after idle the device runs its first applies up to 25 % slower while its
+    clocks ramp (kernel traces show the column pass settling over about
+    20 applies), and the timed steps are meant to measure the steady state."""
+    import torch
+    t0 = time.perf_counter()
+    n = 0
+    while n < max_calls and time.perf_counter() - t0 < seconds:
+        fn()
+        n += 1
+        if n % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
 def time_forward(p, rho, d, ws, steps, warmup):
     import torch
+    settle(lambda: p.forward(rho, d, ws))
     for _ in range(warmup):
         p.forward(rho, d, ws)
     torch.cuda.synchronize()
@@ -156,6 +173,7 @@ def batched_step(steps, warmup):
         res = {}
         for op in ("forward", "adjoint"):
             run = (lambda: p.forward(rho, d, ws)) if op == "forward" else (lambda: p.adjoint(d, gout, ws))
+            settle(run)
             for _ in range(warmup):
                 run()
             torch.cuda.synchronize()

@@ -322,3 +322,43 @@ def test_levels_toeplitz_path(gf, orc, nx, ny, nz, levels, mask, chunk, mode, pr
             assert e <= TOL[prec], (t, NAMES[c], e)
     pa.close()
     pb.close()
+
+
+_PAPER_LEVELS = {}
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_paper_scale_levels_sampled(gf, orc, prec):
+    """The survey the benchmark times: 1024x1024x100, 20 m cells, h = 10 m,
+    100 observation levels, six components, the complete model (20 prisms
+    plus the Gaussian random field); FP64 runs the depth products through
+    the transform in depth, FP32 the direct Toeplitz product.  64 seeded
+    stations on the lowest and the highest level against the
+    oracle's tabulated direct sum with the stations raised by t dz (level t
+    sees the model under t empty layers)."""
+    g = PRESETS["paper_scale"]
+    levels = g.nz
+    rho = prisms_and_grf(g.nx, g.ny, g.nz, 20, 302, 303)
+    st = sample_stations(g.nx, g.ny, 55, seed=307)
+    ts = (0, levels - 1)
+    for t in ts:
+        if t not in _PAPER_LEVELS:
+            note("paper-scale levels: oracle tabulated sum at level %d, %d stations" % (t, len(st)))
+            gt = Geometry(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h + t * g.dz)
+            _PAPER_LEVELS[t] = orc.forward_tabulated(gt, rho, st, mask=0x3F)
+    dt = torch.float64 if prec == "f64" else torch.float32
+    note("paper-scale levels %s: plan and forward" % prec)
+    p = gf.plan_levels(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, levels, 0x3F, prec)
+    assert p.level_path == (4 if prec == "f64" else 3), p.level_path
+    d = p.forward(torch.from_numpy(rho).to("cuda", dt))   # [levels][6][ny][nx] on the device
+    sy = torch.from_numpy(st[:, 1]).cuda()
+    sx = torch.from_numpy(st[:, 0]).cuda()
+    for t in ts:
+        got = d[t][:, sy, sx].double().cpu().numpy()    # [6][nst]
+        for c in range(6):
+            e = rel(got[c], _PAPER_LEVELS[t][:, c])
+            note("paper-scale levels %s level %d %s rel %.2e" % (prec, t, NAMES[c], e))
+            assert e <= TOL[prec], (t, NAMES[c], e)
+    del d
+    p.close()
+    torch.cuda.empty_cache()
