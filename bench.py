@@ -500,6 +500,9 @@ def main():
         "plan_ms": round(main_res["plan_ms"], 1),
         "spectra_bytes": main_res["spectra_bytes"],
         "pass_ms": [round(float(x), 4) for x in main_res["passes"].mean(axis=0)],
+        # stored-kernel counts of the paper (eq. 5 dense, eq. 9 and eq. 11
+        # origin kernels, eq. 22 BTTB, eq. 20 ratio) beside the resident bytes
+        "storage": p.storage(),
     }
     # the plan again in the warm process: the first plan of a process also
     # pays the device's first large allocations
@@ -574,6 +577,8 @@ def main():
                                    "adjoint_pass_ms": [round(float(x), 3) for x in r["adjoint_passes"].mean(axis=0)],
                                    "level_path": r["plan"].level_path, "level_chunk": r["plan"].level_chunk,
                                    "plan_ms": round(r["plan_ms"], 1), "spectra_bytes": r["spectra_bytes"]}
+                if name == "all6" and prec == "f64":
+                    lev["storage"] = r["plan"].storage()
                 r["plan"].close()
                 del r
         line["levels"] = lev

@@ -31,10 +31,11 @@ from .operator import (
     plan,
     plan_layered,
     plan_levels,
+    storage_counts,
 )
 
 __all__ = [
     "ALL6", "ALL7", "ALL9", "COMPONENTS", "GZ", "GXX", "GXY", "GXZ", "GYY", "GYZ", "GZZ", "GX", "GY",
     "GravityForward", "GravityOperator", "Plan", "adjoint", "components_mask",
-    "forward", "plan", "plan_layered", "plan_levels",
+    "forward", "plan", "plan_layered", "plan_levels", "storage_counts",
 ]

@@ -119,6 +119,28 @@ class Plan:
     def plan_ms(self):
         return float(self.info.plan_ms)
 
+    def storage(self):
+        """The paper's stored-kernel counts for this geometry beside what the
+        plan keeps resident.  The counts are per component and are scaled by
+        the resident spectral components and the element size into bytes;
+        `resident_bytes` is the device memory the plan holds for its spectra
+        (one real per frequency of the quarter plane, rows padded to the
+        column pass's pitch, plus the depth-transformed spectra of a levels
+        plan that transforms in depth)."""
+        i = self.info
+        c = storage_counts(i.nx, i.ny, i.nz, i.n_levels)
+        elem = 8 if self.precision == "f64" else 4
+        out = {k: c[k] for k in ("dense", "ega", "ega_virtual", "bttb")}
+        out["ratio"] = c["ratio"]
+        out["components"] = int(i.n_spec)
+        out["element_bytes"] = elem
+        for k in ("dense", "bttb"):
+            out[k + "_bytes"] = c[k] * i.n_spec * elem
+        out["quarter_plane_per_layer"] = (i.px // 2 + 1) * (i.py // 2 + 1)
+        out["resident_bytes"] = int(i.spectra_bytes)
+        out["resident_over_bttb"] = int(i.spectra_bytes) / (c["bttb"] * i.n_spec * elem)
+        return out
+
     def workspace_bytes(self, op, batch):
         out = ctypes.c_size_t()
         opc = nat.GF_OP_FORWARD if op in ("forward", 0) else nat.GF_OP_ADJOINT
@@ -216,6 +238,36 @@ class Plan:
                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                   "gf_debug_spectrum")
         return out
+
+
+def storage_counts(nx, ny, nz, levels=1):
+    """Kernel values one component needs stored under each scheme the paper
+    compares, for nx x ny stations on `levels` planes over nx x ny x nz cells.
+
+    dense        eq. 5: the whole matrix, N_d x N_m (section 2.1; with several
+                 planes N_d counts every station, as in the 1.1e16 figure of
+                 section 2.2 for 100 planes over 1024 x 1024 x 100 cells)
+    ega          eq. 9: the kernel of the computation origin against every
+                 cell, valid through the potential-field symmetry (section 2.2.1)
+    ega_virtual  eq. 11: the origin against the cells of the virtual grid,
+                 translation only (section 2.2.2)
+    bttb         eq. 22: first row and column of every Toeplitz level,
+                 (2nx-1)(2ny-1) per layer offset; a plane of stations sees nz
+                 offsets, `levels` planes see nz + levels - 1 (n - t + 1 of
+                 eq. 10)
+    ratio        eq. 20: the BTTB count of one layer block over its dense count
+    """
+    nx, ny, nz, levels = int(nx), int(ny), int(nz), int(levels)
+    nd = nx * ny * levels
+    nm = nx * ny * nz
+    offsets = nz + levels - 1
+    return {
+        "dense": nd * nm,
+        "ega": nm,
+        "ega_virtual": 2 * nx * 2 * ny * 2 * nz,
+        "bttb": (2 * nx - 1) * (2 * ny - 1) * offsets,
+        "ratio": (2 * nx - 1) / (nx * nx) * (2 * ny - 1) / (ny * ny),
+    }
 
 
 def plan(nx, ny, nz, dx, dy, dz, h, components=ALL6, precision="f64", max_batch=0, device=None, stream=None):

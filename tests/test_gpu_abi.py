@@ -231,3 +231,26 @@ def test_nan_density_propagates(gf, prec):
     assert torch.isnan(gg[0]).all()
     assert torch.equal(gg[1:], clean_g)
     p.close()
+
+
+@pytest.mark.parametrize("nx,ny,nz,prec,mask", [(40, 40, 20, "f64", 0x3F), (96, 50, 7, "f32", 0x1FF),
+                                                (1024, 1024, 100, "f64", 0x3F)])
+def test_resident_storage_against_eq22(gf, nx, ny, nz, prec, mask):
+    """The plan's resident spectra beside the paper's counts: one real per
+    frequency of the quarter plane per layer and resident component (rows
+    padded to the column pass's pitch), which
+    is at most about a quarter of the BTTB count of eq. 22 and far below
+    the dense count of eq. 5."""
+    p = gf.plan(nx, ny, nz, 20.0, 20.0, 20.0, 10.0, mask, prec)
+    s = p.storage()
+    i = p.info
+    elem = 8 if prec == "f64" else 4
+    quarter = i.n_spec * nz * (i.px // 2 + 1) * (i.py // 2 + 1) * elem
+    # rows are padded to the column pass's pitch
+    assert quarter <= s["resident_bytes"] <= 1.25 * quarter
+    assert s["quarter_plane_per_layer"] == (i.px // 2 + 1) * (i.py // 2 + 1)
+    assert s["bttb"] == (2 * nx - 1) * (2 * ny - 1) * nz
+    assert s["dense"] == (nx * ny) ** 2 * nz
+    assert s["resident_bytes"] < 0.3 * s["bttb_bytes"] or min(nx, ny) < 64
+    assert s["resident_bytes"] < s["dense_bytes"]
+    p.close()
