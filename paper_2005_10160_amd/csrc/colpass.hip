@@ -559,16 +559,34 @@ inline bool ws_shared_for(int B)
     return ws_shared_exists<T, N>() && B >= 2 && (B % G == 0 || B >= 2 * G);
 }
 
+// Whether resident rows at column length N are stored in the lane order of
+// the in-register wave transform (see spec_pos).
+template <typename T, int N>
+constexpr bool ws_lane_order() { return use_ws<N>() && ws_ppt<T, N>() == 4; }
+
+// Base-4 digit reversal of a 6-bit index (an involution): the lane of the
+// in-register transform's output that holds frequency index x mod 64.
+__host__ __device__ constexpr unsigned digit_rev64(unsigned x)
+{
+    return (x >> 4) + 4u * ((x >> 2) & 3u) + 16u * (x & 3u);
+}
+
 // Position of frequency ky in [0, N/2] within a resident spectrum row:
 // residue blocks r = ky mod NW (block 0 holds N/(2 NW) + 1 values, the
-// others N/(2 NW)), ky / NW within a block.
+// others N/(2 NW)), index j = ky / NW within a block.  Where the wave
+// transform runs in registers its output frequencies sit in lanes in
+// digit-reversed order, so each 64-value chunk of a block is stored in that
+// order: lane l then reads the l-th value of a chunk (its own frequencies)
+// or the (63 - l)-th (the mirrored ones), and the reads of a wave meet
+// distinct LDS banks.
 template <typename T, int N>
 __host__ __device__ constexpr unsigned spec_pos(unsigned ky)
 {
     constexpr unsigned NW = (unsigned)ws_waves<T, N>();
-    if (NW == 1) return ky;
-    const unsigned r = ky % NW, j = ky / NW;
-    return r == 0 ? j : r * (N / NW / 2) + 1u + j;
+    const unsigned r = NW == 1 ? 0u : ky % NW, j = NW == 1 ? ky : ky / NW;
+    const unsigned base = r == 0 ? 0u : r * (N / NW / 2) + 1u;
+    if (ws_lane_order<T, N>() && j < (unsigned)(N / NW / 2)) return base + (j & ~63u) + digit_rev64(j & 63u);
+    return base + j;
 }
 
 // exp(-2 pi i k / n) * x for a compile-time k and n in {1, 2, 4, 8}
@@ -654,27 +672,52 @@ __device__ __forceinline__ void form_z(cx<T> (&v)[PPT], const cx<T> *xc, unsigne
     }
 }
 
-// Offsets of wave w's frequencies in a residue-ordered spectrum row: lower
-// slots (ky = NW k2 + w <= N/2) at lo + k2, upper slots (their mirror N - ky)
-// at hi - k2.
-template <int NW, int L>
-__device__ __forceinline__ void ws_offsets(unsigned w, unsigned &lo, unsigned &hi)
+// Offsets of wave w's frequencies in a residue-ordered spectrum row (slot
+// s of a lane holds k2 = ws_out_lane(lane) + 64 e after the forward
+// transform): lower slots (ky = NW k2 + w <= N/2, block w, index k2) and
+// upper slots (their mirror N - ky: block NW - w, index L - 1 - k2, or block
+// 0, index L - k2, for w = 0), at the positions spec_pos gives them.  In the
+// lane order that is lo + lane + 64 e and hi - lane - 64 e, except for the
+// upper slots of wave 0, whose mirrored indices L - k2 are one off the
+// chunk boundaries.
+template <typename F, int PPT, int NW, int L>
+__device__ __forceinline__ void ws_spec_offsets(unsigned (&off)[PPT], unsigned lane, unsigned w)
 {
-    lo = w == 0 ? 0u : w * (L / 2) + 1u;
-    hi = w == 0 ? (unsigned)L : (NW - w) * (L / 2) + (unsigned)L;
+    const unsigned lo = w == 0 ? 0u : w * (L / 2) + 1u;
+    const unsigned hi = w == 0 ? (unsigned)L : (NW - w) * (L / 2) + (unsigned)L;
+    const unsigned ol = ws_out_lane<F>(lane);
+#pragma unroll
+    for (int s = 0; s < PPT; ++s) {
+        const unsigned e = (unsigned)F::elem_out(s);
+        const bool upper = F::elem_out(s) >= PPT / 2;
+        if constexpr (is_lane_fft<F>::value) {
+            static_assert(L == 256, "the lane order holds for the 256-point in-register transform");
+            if (!upper) {
+                off[s] = lo + lane + 64u * e;
+            } else if (w != 0) {
+                off[s] = hi - lane - 64u * e;
+            } else {
+                const unsigned j = (unsigned)L - ol - 64u * e;
+                off[s] = j < (unsigned)(L / 2) ? (j & ~63u) + digit_rev64(j & 63u) : j;
+            }
+        } else {
+            const unsigned k2 = ol + 64u * e;
+            off[s] = upper ? hi - k2 : lo + k2;
+        }
+    }
 }
 
 // One component's term of the layer reduction in the wave split (see
-// mac_component for the kinds): slot s of this lane holds k2 = lane + 64 e.
+// mac_component for the kinds): slot s of this lane reads its spectrum value
+// at kr[off[s]].
 template <typename F, typename T, int PPT, int NW, bool IM, bool YO, bool ADJ>
-__device__ __forceinline__ void mac_ws(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr, unsigned lane,
-                                       unsigned lo, unsigned hi)
+__device__ __forceinline__ void mac_ws(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr,
+                                       const unsigned (&off)[PPT])
 {
 #pragma unroll
     for (int s = 0; s < PPT; ++s) {
         const bool upper = F::elem_out(s) >= PPT / 2;
-        const unsigned k2 = lane + 64u * F::elem_out(s);
-        T k = upper ? kr[hi - k2] : kr[lo + k2];
+        T k = kr[off[s]];
         if (YO && upper) k = -k;
         if (IM) {
             if (ADJ) {
@@ -693,14 +736,14 @@ __device__ __forceinline__ void mac_ws(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT],
 
 template <typename F, typename T, int PPT, int NW, bool ADJ>
 __device__ __forceinline__ void mac_ws_dispatch(cx<T> (&acc)[PPT], const cx<T> (&x)[PPT], const T *kr,
-                                                unsigned lane, unsigned lo, unsigned hi, bool im, bool yo)
+                                                const unsigned (&off)[PPT], bool im, bool yo)
 {
     if (im) {
-        if (yo) mac_ws<F, T, PPT, NW, true, true, ADJ>(acc, x, kr, lane, lo, hi);
-        else    mac_ws<F, T, PPT, NW, true, false, ADJ>(acc, x, kr, lane, lo, hi);
+        if (yo) mac_ws<F, T, PPT, NW, true, true, ADJ>(acc, x, kr, off);
+        else    mac_ws<F, T, PPT, NW, true, false, ADJ>(acc, x, kr, off);
     } else {
-        if (yo) mac_ws<F, T, PPT, NW, false, true, ADJ>(acc, x, kr, lane, lo, hi);
-        else    mac_ws<F, T, PPT, NW, false, false, ADJ>(acc, x, kr, lane, lo, hi);
+        if (yo) mac_ws<F, T, PPT, NW, false, true, ADJ>(acc, x, kr, off);
+        else    mac_ws<F, T, PPT, NW, false, false, ADJ>(acc, x, kr, off);
     }
 }
 
@@ -931,9 +974,8 @@ __global__ void __launch_bounds__((WsCfg<T, N, SH>::THREADS))
 #pragma unroll
         for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
     }
-    unsigned lo, hi;
-    ws_offsets<NW, L>(w, lo, hi);
-    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    unsigned off[PPT];   // this lane's slots in a resident spectrum row
+    ws_spec_offsets<F, PPT, NW, L>(off, lane, w);
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
@@ -986,7 +1028,7 @@ __global__ void __launch_bounds__((WsCfg<T, N, SH>::THREADS))
 #pragma unroll
         for (int c = 0; c < CMAX; ++c)
             if (c < Cs)
-                mac_ws_dispatch<F, T, PPT, NW, false>(acc[c], v, scur + c * QP, ol, lo, hi, (im_m >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, false>(acc[c], v, scur + c * QP, off, (im_m >> c) & 1u,
                                                       (yo_m >> c) & 1u);
         if (n + 1 < n1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
         if constexpr (NB == 2) {
@@ -1068,9 +1110,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
     }
-    unsigned lo, hi;
-    ws_offsets<NW, L>(w, lo, hi);
-    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    unsigned off[PPT];   // this lane's slots in a resident spectrum row
+    ws_spec_offsets<F, PPT, NW, L>(off, lane, w);
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
@@ -1122,7 +1163,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             if (k < nk) {
                 const int j = k / Cs, c = k - j * Cs;
                 const T *srow = sbuf + (size_t)((n + j) % ring) * rowvals + (size_t)c * QP;
-                mac_ws_dispatch<F, T, PPT, NW, false>(acc[k], v, srow, ol, lo, hi, (imag_mask >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, false>(acc[k], v, srow, off, (imag_mask >> c) & 1u,
                                                       (yodd_mask >> c) & 1u);
             }
         if (n + 1 < n1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
@@ -1193,9 +1234,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
     }
-    unsigned lo, hi;
-    ws_offsets<NW, L>(w, lo, hi);
-    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    unsigned off[PPT];   // this lane's slots in a resident spectrum row
+    ws_spec_offsets<F, PPT, NW, L>(off, lane, w);
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
@@ -1253,7 +1293,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int c = 0; c < CMAX; ++c)
             if (c < Cs)
-                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[c], scur + c * QP, ol, lo, hi, (im_m >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[c], scur + c * QP, off, (im_m >> c) & 1u,
                                                      (yo_m >> c) & 1u);
         if constexpr (NB == 1) {
             // one buffer: the next layer's rows stream in during this
@@ -1315,9 +1355,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
     }
-    unsigned lo, hi;
-    ws_offsets<NW, L>(w, lo, hi);
-    const unsigned ol = ws_out_lane<F>(lane);   // frequency lane index of the transform's output
+    unsigned off[PPT];   // this lane's slots in a resident spectrum row
+    ws_spec_offsets<F, PPT, NW, L>(off, lane, w);
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
@@ -1378,7 +1417,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
             if (k < nk) {
                 const int j = k / Cs, c = k - j * Cs;
                 const T *srow = sbuf + (size_t)((n + j) % ring) * rowvals + (size_t)c * QP;
-                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[k], srow, ol, lo, hi, (imag_mask >> c) & 1u,
+                mac_ws_dispatch<F, T, PPT, NW, true>(v, rh[k], srow, off, (imag_mask >> c) & 1u,
                                                      (yodd_mask >> c) & 1u);
             }
         ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre, ltw);
@@ -1439,13 +1478,12 @@ __device__ __forceinline__ SpItem sp_item(unsigned g, int M, int B)
 }
 
 // Offset of slot s's frequency in a two-row spectrum (see above): row 0 at
-// lo + k2, row 1 at QP + hi - k2.
+// the lower slots' resident positions, row 1 at QP + the upper slots'.
 template <typename F, int PPT, int QP>
-__device__ __forceinline__ unsigned sp_offset(int s, unsigned ol, unsigned lo, unsigned hi)
+__device__ __forceinline__ unsigned sp_offset(int s, const unsigned (&off)[PPT])
 {
     const bool upper = F::elem_out(s) >= PPT / 2;
-    const unsigned k2 = ol + 64u * F::elem_out(s);
-    return upper ? (unsigned)QP + hi - k2 : lo + k2;
+    return upper ? (unsigned)QP + off[s] : off[s];
 }
 
 // Spectra of the columns of slabs [s0, s1) (s0, s1 from blockIdx.y and
@@ -1485,9 +1523,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
 #pragma unroll
         for (int n1 = 0; n1 < NW / 2; ++n1) cn[n1] = tw[(((unsigned)L * n1 * w) & (N - 1)) << (twlog - LOGN)];
     }
-    unsigned lo, hi;
-    ws_offsets<NW, L>(w, lo, hi);
-    const unsigned ol = ws_out_lane<F>(lane);
+    unsigned off[PPT];   // this lane's slots in a resident spectrum row
+    ws_spec_offsets<F, PPT, NW, L>(off, lane, w);
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<false>(ltw, tw, twlog, lane);
 
@@ -1519,7 +1556,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
         if (it.active) {
             cx<T> *dst = X + (((size_t)it.b * nsrc + sl) * (M + 1) + row) * (2 * QP);
 #pragma unroll
-            for (int s = 0; s < PPT; ++s) dst[sp_offset<F, PPT, QP>(s, ol, lo, hi)] = v[s];
+            for (int s = 0; s < PPT; ++s) dst[sp_offset<F, PPT, QP>(s, off)] = v[s];
         }
         if (sl + 1 < s1) put_tail(cbuf + (cur ^ 1) * (N / 2), ny, tg, tail);
         stage_wait<true>();
@@ -1553,9 +1590,8 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
     F::load_stage_table(twq, tw, twlog, threadIdx.x, C::THREADS);
     WsTwiddles<T, N, PPT> tws;
     if constexpr (NW > 1) tws.init(tw, twlog, lane, w);
-    unsigned lo, hi;
-    ws_offsets<NW, L>(w, lo, hi);
-    const unsigned ol = ws_out_lane<F>(lane);
+    unsigned off[PPT];   // this lane's slots in a resident spectrum row
+    ws_spec_offsets<F, PPT, NW, L>(off, lane, w);
     cx<T> ltw[C::LANE ? 9 : 1];
     if constexpr (C::LANE) lane_twiddles<true>(ltw, tw, twlog, lane);
     __syncthreads();   // stage table
@@ -1568,7 +1604,7 @@ __global__ void __launch_bounds__((WsCfg<T, N>::THREADS))
         const cx<T> *src = X + (((size_t)it.b * nsrc + sl) * (M + 1) + row) * (2 * QP);
         cx<T> v[PPT];
 #pragma unroll
-        for (int s = 0; s < PPT; ++s) v[s] = src[sp_offset<F, PPT, QP>(s, ol, lo, hi)];
+        for (int s = 0; s < PPT; ++s) v[s] = src[sp_offset<F, PPT, QP>(s, off)];
         ws_inverse_put<F, T, N, NW, L, PPT>(v, xch, twp, twlog, lane, w, tws, cre, ltw);
         lds_barrier();
         if (it.active)
