@@ -444,13 +444,16 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #define GF_WS_PPT32 8
 #endif
 // Points per lane of the wave transforms for column length N: four in FP64
-// (two waves per SIMD fit the accumulators), eight in FP32 (fewer exchanges
-// and column reads through LDS), adjusted so that a column has one to eight
-// waves.  The spectrum layout follows it, so it is fixed per plan precision.
+// (two waves per SIMD fit the accumulators); in FP32 four up to length 1024
+// (in-register transforms; the batched 512 x 512 x 128 adjoint column pass
+// 6.25 -> 4.75 ms against eight) and eight beyond (fewer column reads
+// through LDS: the 2048-point forward 0.69 -> 0.68 ms against four),
+// adjusted so that a column has one to eight waves.  The spectrum layout
+// follows it, so it is fixed per plan precision and column length.
 template <typename T, int N>
 constexpr int ws_ppt()
 {
-    int p = sizeof(T) == 8 ? GF_WS_PPT64 : GF_WS_PPT32;
+    int p = sizeof(T) == 8 ? GF_WS_PPT64 : (N <= 1024 ? 4 : GF_WS_PPT32);
     while (p > 1 && 64 * p > N) p /= 2;
     while (N / (64 * p) > 8) p *= 2;
     return p;
