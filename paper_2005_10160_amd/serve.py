@@ -89,6 +89,8 @@ class Request:
     t_done: Optional[float] = None
     cache: Optional[str] = None   # "hit": spectra resident on arrival; "miss": they had to be built
     keep_result: bool = True      # False: the output buffer is recycled once done (load replay)
+    device_ms: Optional[float] = None   # its group's time on the device: input copies, operator, output copies
+    compute_ms: Optional[float] = None  # its group's operator time on the device
     event: threading.Event = field(default_factory=threading.Event, repr=False)
 
     @property
@@ -485,18 +487,24 @@ class GpuExecutor:
         else:
             shape_in = (B,) + key.data_shape
             shape_out = (B, key.nz, key.ny, key.nx)
+        # device-side timing of the group: its input copies, the operator,
+        # its output copies
+        tev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
         with torch.cuda.stream(st):
             x = torch.empty(shape_in, dtype=self.dtype, device=self.device)
             y = torch.empty(shape_out, dtype=self.dtype, device=self.device)
             ws = torch.empty(p.workspace_bytes(op, B), dtype=torch.uint8, device=self.device)
+            tev[0].record(st)
             o = 0
             for r in reqs:
                 x[o:o + r.batch].copy_(r.data, non_blocking=True)
                 o += r.batch
+            tev[1].record(st)
             if op == "forward":
                 p.forward(x, y, ws, stream=st)
             else:
                 p.adjoint(x, y, ws, stream=st)
+            tev[2].record(st)
             o = 0
             for r in reqs:
                 if r.result is None:
@@ -505,17 +513,19 @@ class GpuExecutor:
                     r.result = free.pop() if free else torch.empty(shp, dtype=self.dtype, pin_memory=True)
                 r.result.copy_(y[o:o + r.batch], non_blocking=True)
                 o += r.batch
-            ev = torch.cuda.Event()
-            ev.record(st)
-        self.events[slot] = ev
-        self.keep[slot] = (x, y, ws, reqs)
+            tev[3].record(st)
+        self.events[slot] = tev[3]
+        self.keep[slot] = (x, y, ws, reqs, tev)
 
     def poll(self, slot):
         ev = self.events[slot]
         if ev is None or ev.query():
             kept = self.keep[slot]
             if kept is not None:
+                tev = kept[4]
+                dev_ms, comp_ms = tev[0].elapsed_time(tev[3]), tev[1].elapsed_time(tev[2])
                 for r in kept[3]:
+                    r.device_ms, r.compute_ms = dev_ms, comp_ms
                     if not r.keep_result and r.result is not None:
                         self.out_pool[tuple(r.result.shape)].append(r.result)
                         r.result = None
@@ -596,13 +606,21 @@ def _percentiles(vals):
 def latency_summary(records):
     """p50 / p99 latency (ms) of completed requests, overall and split by
     whether their spectra were resident on arrival (hit) or had to be built
-    (miss)."""
+    (miss); overall also the device-only figures where the records carry
+    them: the request's time on the device (its group's input copies,
+    operator and output copies) and its group's operator time."""
     out = {}
     for name, sel in (("all", lambda r: True), ("hit", lambda r: r["cache"] == "hit"),
                       ("miss", lambda r: r["cache"] == "miss")):
         lat = [r["latency_ms"] for r in records if r["status"] == "done" and sel(r)]
         p50, p99 = _percentiles(lat)
         out[name] = {"n": len(lat), "p50_ms": p50, "p99_ms": p99}
+    for key in ("device_ms", "compute_ms"):
+        vals = [r[key] for r in records if r["status"] == "done" and r.get(key) is not None]
+        if vals:
+            p50, p99 = _percentiles(vals)
+            out["all"][key.replace("_ms", "_p50_ms")] = p50
+            out["all"][key.replace("_ms", "_p99_ms")] = p99
     return out
 
 
@@ -712,6 +730,11 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
             "t_admit": (min(admits) - t0) if admits else None,
             "t_done": (t_done - t0) if done else None,
             "latency_ms": (t_done - parts[0].t_arrival) * 1e3 if done else None,
+            # the plain baseline runs a request's models one call after another
+            "device_ms": sum(r.device_ms for r in parts) if done and all(r.device_ms is not None for r in parts)
+            else None,
+            "compute_ms": sum(r.compute_ms for r in parts) if done and all(r.compute_ms is not None for r in parts)
+            else None,
         })
         if done:
             k = parts[0].key
@@ -720,6 +743,8 @@ def replay(trace, inputs, executor_factory, budget_bytes, batched=True, n_slots=
     completed = lat["all"]["n"]
     return {"requests": len(reqs), "completed": completed, "wall_s": wall,
             "p50_ms": lat["all"]["p50_ms"], "p99_ms": lat["all"]["p99_ms"],
+            "device_p50_ms": lat["all"].get("device_p50_ms"), "device_p99_ms": lat["all"].get("device_p99_ms"),
+            "compute_p50_ms": lat["all"].get("compute_p50_ms"), "compute_p99_ms": lat["all"].get("compute_p99_ms"),
             "hit": lat["hit"], "miss": lat["miss"],
             "requests_per_s": completed / wall, "effective_evals_per_s": evals / wall, "stats": stats,
             "records": records}

@@ -65,6 +65,11 @@ def test_served_equals_alone(gf, orc):
     note("server stats: %s" % stats)
     assert all(r.status == "done" for r in reqs), [(r.rid, r.status, r.error) for r in reqs]
     assert stats.get("batched_requests", 0) == len(reqs)
+    # device-side times of each request's group: copies and operator within
+    # the request's wall-clock latency
+    for r in reqs:
+        assert r.device_ms is not None and r.compute_ms is not None, r.rid
+        assert 0.0 < r.compute_ms <= r.device_ms <= r.latency * 1e3 + 1.0, (r.rid, r.compute_ms, r.device_ms)
     ex.close()
 
     plans = {}

@@ -377,3 +377,16 @@ def test_latency_summary_splits_hits_and_misses():
     s = latency_summary(recs)
     assert (s["all"]["n"], s["hit"]["n"], s["miss"]["n"]) == (110, 100, 10)
     assert s["hit"]["p50_ms"] == pytest.approx(50.5) and s["miss"]["p50_ms"] == pytest.approx(1004.5)
+
+
+def test_latency_summary_device_figures():
+    from paper_2005_10160_amd.serve import latency_summary
+    recs = [{"status": "done", "cache": "hit", "latency_ms": 10.0 + v, "device_ms": 2.0 + v, "compute_ms": 1.0}
+            for v in range(100)]
+    recs += [{"status": "rejected", "cache": "miss", "latency_ms": None, "device_ms": None, "compute_ms": None}]
+    s = latency_summary(recs)
+    assert s["all"]["device_p50_ms"] == pytest.approx(51.5)
+    assert s["all"]["compute_p99_ms"] == pytest.approx(1.0)
+    # records without device figures (the scheduler's virtual clock) give none
+    s = latency_summary([{"status": "done", "cache": "hit", "latency_ms": 1.0}])
+    assert "device_p50_ms" not in s["all"]
