@@ -366,7 +366,7 @@ def main():
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the operator runs on a single MI355X and has no "
-              "multi-GPU path in this build (--gpus %d requested)" % args.gpus, file=sys.stderr)
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import torch
