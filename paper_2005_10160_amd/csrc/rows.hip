@@ -137,7 +137,7 @@ struct RowCfg {
     static constexpr int WAVES_PER_EU = THREADS <= 512 ? 2 * THREADS / 256 : 1;
 };
 
-template <typename T, int M>
+template <typename T, int M, bool HALF>
 __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
     __attribute__((amdgpu_waves_per_eu(RowCfgF<T, M>::WAVES_PER_EU)))
     row_r2c_kernel(const T *__restrict__ in, long row_len, int lin, int rows, int ldc, int nsub, int src_per_b,
@@ -162,6 +162,11 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
     }
     T *sre = lds + (size_t)g * W;
 
+    // Loads and the transform.  With HALF (lin <= M: a row whose nonzero
+    // samples lie in its first half, the zero padding of the circulant
+    // embedding) the packed inputs of the upper half of the half-length
+    // transform are zero: they are taken as literal zeros (no loads) and the
+    // first stage folds them away.
     cx<T> v[PPT];
     if (gr < nrows_total) {
         const long per_b = (long)nsub * rows;
@@ -182,13 +187,16 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
             cx<T> pr[PPT];
 #pragma unroll
             for (int sl = 0; sl < PPT; ++sl) {
+                if (HALF && F::elem_in(sl) >= PPT / 2) continue;
                 const unsigned j = t + NT * F::elem_in(sl);
                 pr[sl] = *reinterpret_cast<const cx<T> *>(r0 + 2 * (2 * j < (unsigned)lin ? j : 0u));
             }
 #pragma unroll
             for (int sl = 0; sl < PPT; ++sl) {
                 const unsigned j = t + NT * F::elem_in(sl);
-                v[sl] = 2 * j < (unsigned)lin ? cx<T>{w0 * pr[sl].re, w0 * pr[sl].im} : cx<T>{T(0), T(0)};
+                v[sl] = (HALF && F::elem_in(sl) >= PPT / 2) || 2 * j >= (unsigned)lin
+                            ? cx<T>{T(0), T(0)}
+                            : cx<T>{w0 * pr[sl].re, w0 * pr[sl].im};
             }
         } else {
             T e0[PPT], o0[PPT];
@@ -223,7 +231,9 @@ __global__ void __launch_bounds__((RowCfgF<T, M>::THREADS))
 #pragma unroll
             for (int sl = 0; sl < PPT; ++sl) {
                 const unsigned j = t + NT * F::elem_in(sl);
-                v[sl] = cx<T>{2 * j < (unsigned)lin ? e0[sl] : T(0), 2 * j + 1 < (unsigned)lin ? o0[sl] : T(0)};
+                v[sl] = (HALF && F::elem_in(sl) >= PPT / 2)
+                            ? cx<T>{T(0), T(0)}
+                            : cx<T>{2 * j < (unsigned)lin ? e0[sl] : T(0), 2 * j + 1 < (unsigned)lin ? o0[sl] : T(0)};
             }
         }
     } else {
@@ -450,9 +460,14 @@ static int run_r2c(const void *in, long row_len, int lin, int rows, int ldc, int
     const long nblk = (nrows + C::TR - 1) / C::TR;
     const size_t lds = (size_t)C::TR * C::ROW_BYTES + (size_t)C::TWW * sizeof(T);
     if (lds > lds_limit()) return -3;
-    hipLaunchKernelGGL((row_r2c_kernel<T, M>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
-                       (const T *)in, row_len, lin, rows, ldc, nsub, src_per_b, nrows, cmb, (cx<T> *)out,
-                       out_bslabs > 0 ? out_bslabs : (long)nsub, (const cx<T> *)tw, twlog);
+    if (lin <= M)
+        hipLaunchKernelGGL((row_r2c_kernel<T, M, true>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
+                           (const T *)in, row_len, lin, rows, ldc, nsub, src_per_b, nrows, cmb, (cx<T> *)out,
+                           out_bslabs > 0 ? out_bslabs : (long)nsub, (const cx<T> *)tw, twlog);
+    else
+        hipLaunchKernelGGL((row_r2c_kernel<T, M, false>), dim3((unsigned)nblk), dim3(C::THREADS), lds, st,
+                           (const T *)in, row_len, lin, rows, ldc, nsub, src_per_b, nrows, cmb, (cx<T> *)out,
+                           out_bslabs > 0 ? out_bslabs : (long)nsub, (const cx<T> *)tw, twlog);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
