@@ -49,9 +49,13 @@ __device__ __forceinline__ Term<T> combo_term(const RowCombo &cmb, int o)
 // exchanged one after the other through one LDS array per row.  Rows per
 // workgroup: within 40 KB of LDS and 512 threads, so that two workgroups
 // share a CU and one's loads and stores overlap the other's transforms.
+// FP32 rows of 1024 points also take 16 points a lane: half a wave per row
+// gives sixteen rows a workgroup, whose transposed stores then cover whole
+// 128-byte lines (8-byte units of 16 consecutive rows; batched 512 x 512 x
+// 128 FP32 row pass 3.07-3.12 -> 2.90 ms).
 template <typename T, int M>
 struct RowCfgF {
-    static constexpr int PPT = (M >= 1024) ? 16 : ((M >= 8) ? 8 : M);
+    static constexpr int PPT = (M >= 1024 || (M == 512 && sizeof(T) == 4)) ? 16 : ((M >= 8) ? 8 : M);
     static constexpr int NT = M / PPT;
     static constexpr int RADIX = PPT >= 8 ? 8 : PPT;
     // stage twiddles from a per-stage table in LDS, filled once per
@@ -59,7 +63,9 @@ struct RowCfgF {
     // arithmetic per butterfly, cost FP64 0.62 -> 0.57 ms and FP32
     // 0.37 -> 0.33 ms at 1024 x 1024 x 100)
     static constexpr bool TWS = true;
-    using FFT = BlockFFT<T, M, NT, RADIX, true, TWS, NT == 64>;
+    // a row's lanes lie within one wave: its exchanges need only the wave's
+    // own LDS ordering
+    using FFT = BlockFFT<T, M, NT, RADIX, true, TWS, (64 % NT) == 0>;
     static constexpr int TWW = TWS ? ((2 * FFT::stw_entries() + 16 / (int)sizeof(T) - 1) / (16 / (int)sizeof(T))) * (16 / (int)sizeof(T)) : 0;
     static constexpr int W = FFT::lds_words();
     static constexpr int E = 256 / (int)sizeof(T);   // elements of one 256-byte bank row
