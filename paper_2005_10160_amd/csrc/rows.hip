@@ -83,10 +83,13 @@ struct RowCfgF {
     static constexpr int TR0 = tr_with(40, 512);
     static constexpr int TR = M >= 2048 ? tr_with(80, 512) : TR0;
     static constexpr int THREADS = TR * NT;
-    // row stride = E/TR mod E: the transposed reads (TR rows x E/TR units per
-    // bank cycle) then fall in distinct banks
-    static constexpr int SHIFT = E / TR > 0 ? E / TR : 1;
-    static constexpr int WS = W + ((SHIFT - W % E) % E + E) % E;
+    // row stride = SHIFT mod lc elements, where one LDS cycle serves lc =
+    // 128 / sizeof(T) lanes (32 lanes of 4 bytes, 16 of 8) and SHIFT = lc /
+    // TR, at least 16 bytes (aligned rows): the lanes of one cycle of the
+    // transposed reads, TR rows x SHIFT units, then fall in distinct banks
+    static constexpr int LC = 128 / (int)sizeof(T);
+    static constexpr int SHIFT = LC / TR > 16 / (int)sizeof(T) ? LC / TR : 16 / (int)sizeof(T);
+    static constexpr int WS = W + ((SHIFT - W % LC) % LC + LC) % LC;
     static constexpr int ROW_BYTES = WS * (int)sizeof(T);
     // register target: waves per SIMD for two resident workgroups (one for
     // the larger row groups)
@@ -122,12 +125,17 @@ struct RowCfg {
     // one word beyond the transform's arrays: element M holds the packed
     // Nyquist bin X[M] before the half-length spectrum is formed
     static constexpr int W = FFT::lds_words() + 1;
-    // row stride (re and im arrays) = 8 mod the elements of one 256-byte bank
-    // row: the transposed gather (rows fastest, 8 units a wave) then hits
-    // distinct banks
-    static constexpr int E = 256 / (int)sizeof(T);
-    static constexpr int RWS = 2 * W + ((E + 8 - (2 * W) % E) % E);
-    static constexpr int ROW_BYTES = RWS * (int)sizeof(T);
+    // row stride (re and im arrays) for a group of tr rows: S mod lc
+    // elements, where one LDS cycle serves lc = 128 / sizeof(T) lanes (32
+    // lanes of 4 bytes, 16 of 8) and S = lc / tr, at least 16 bytes (aligned
+    // rows): the lanes of one cycle of the transposed gather, tr rows x S
+    // units, then fall in distinct banks
+    static constexpr int stride_for(int tr)
+    {
+        const int lc = 128 / (int)sizeof(T), al = 16 / (int)sizeof(T);
+        const int sh = lc / tr > al ? lc / tr : al;
+        return 2 * W + ((lc + sh - (2 * W) % lc) % lc);
+    }
     // rows per workgroup: a power of two within 80 KB of LDS (two workgroups
     // per CU) and 1024 threads, 512 in FP32 (two workgroups then share a CU
     // where registers leave room for one of 1024 threads: batched 512 x 512
@@ -136,11 +144,13 @@ struct RowCfg {
     static constexpr int tr_calc()
     {
         int tr = 64;
-        while (tr > 1 && (tr * ROW_BYTES > 80 * 1024 || tr * NT > MAXT)) tr /= 2;
+        while (tr > 1 && (tr * stride_for(tr) * (int)sizeof(T) > 80 * 1024 || tr * NT > MAXT)) tr /= 2;
         return tr;
     }
     static constexpr int TR = tr_calc();
     static constexpr int THREADS = TR * NT;
+    static constexpr int RWS = stride_for(TR);
+    static constexpr int ROW_BYTES = RWS * (int)sizeof(T);
     // register target: two resident workgroups (512-thread FP64 workgroups
     // need at most 128 registers a lane); larger workgroups fit one
     static constexpr int WAVES_PER_EU = THREADS <= 512 ? 2 * THREADS / 256 : 1;
