@@ -109,12 +109,16 @@ __device__ __forceinline__ unsigned xcd_block()
     return xcd * q + min(xcd, rem) + k;
 }
 
-// Inverse rows: 8 points a lane, full complex exchange.
+// Inverse rows: full complex exchange; 8 points a lane, 16 for FP32 rows of
+// 1024 points and more: half as many lanes a row gives twice the rows a
+// workgroup, so that the transposed gather reads runs of twice the length
+// (FP32 inverse rows at 1024^2 x 100 0.44 -> 0.33 ms, 100 levels 2.67 ->
+// 2.00 ms, batched 512^2 x 128 3.37 -> 2.96 ms).
 template <typename T, int M>
 struct RowCfg {
-    static constexpr int PPT = (M >= 8) ? 8 : M;
+    static constexpr int PPT = (M >= 512 && sizeof(T) == 4) ? 16 : ((M >= 8) ? 8 : M);
     static constexpr int NT = M / PPT;
-    static constexpr int RADIX = PPT;
+    static constexpr int RADIX = PPT >= 8 ? 8 : PPT;
     // FP32: stage twiddles from a per-stage table in LDS (batched inverse
     // rows at 512 x 512 x 128 4.18 -> 3.81 ms); in FP64 the table's LDS
     // leaves fewer workgroups per CU (100-level inverse rows 3.9 -> 5.7 ms)
@@ -357,40 +361,45 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
         off1 = (((long)b * nsrc + tm.s1) * M + u0) * (long)ldc + y;
     }
     const long ustep = (long)NT * ldc;
-    cx<T> acc[PPT];
+    // items gathered per pass over the splits (bounds the registers the
+    // gather holds)
+    constexpr int GH = PPT > 8 ? 8 : PPT;
 #pragma unroll
-    for (int i = 0; i < PPT; ++i) acc[i] = cx<T>{T(0), T(0)};
-    for (int sp = 0; sp < nsplit; ++sp) {
-        const cx<T> *D0 = D + sp * split_stride + off0;
-        cx<T> x0[PPT];
+    for (int h = 0; h < PPT; h += GH) {
+        cx<T> acc[GH];
 #pragma unroll
-        for (int i = 0; i < PPT; ++i) x0[i] = D0[i * ustep];
-        if (two) {
-            const cx<T> *D1 = D + sp * split_stride + off1;
-            cx<T> x1[PPT];
+        for (int i = 0; i < GH; ++i) acc[i] = cx<T>{T(0), T(0)};
+        for (int sp = 0; sp < nsplit; ++sp) {
+            const cx<T> *D0 = D + sp * split_stride + off0 + h * ustep;
+            cx<T> x0[GH];
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) x1[i] = D1[i * ustep];
+            for (int i = 0; i < GH; ++i) x0[i] = D0[i * ustep];
+            if (two) {
+                const cx<T> *D1 = D + sp * split_stride + off1 + h * ustep;
+                cx<T> x1[GH];
 #pragma unroll
-            for (int i = 0; i < PPT; ++i) acc[i] = add(acc[i], scale(x1[i], wb));
+                for (int i = 0; i < GH; ++i) x1[i] = D1[i * ustep];
+#pragma unroll
+                for (int i = 0; i < GH; ++i) acc[i] = add(acc[i], scale(x1[i], wb));
+            }
+#pragma unroll
+            for (int i = 0; i < GH; ++i) acc[i] = add(acc[i], scale(x0[i], wa));
         }
 #pragma unroll
-        for (int i = 0; i < PPT; ++i) acc[i] = add(acc[i], scale(x0[i], wa));
-    }
-
-#pragma unroll
-    for (int i = 0; i < PPT; ++i) {
-        const unsigned r = r0, u = u0 + i * NT;
-        T *qre = lds + (size_t)r * C::RWS;
-        T *qim = qre + W;
-        if (u == 0) {  // packed: X[0] = re, X[M] = im, both real
-            qre[0] = acc[i].re;
-            qim[0] = T(0);
-            qre[F::pad(M)] = acc[i].im;
-            qim[F::pad(M)] = T(0);
-        } else {
-            const unsigned idx = F::pad(u);
-            qre[idx] = acc[i].re;
-            qim[idx] = acc[i].im;
+        for (int i = 0; i < GH; ++i) {
+            const unsigned r = r0, u = u0 + (h + i) * NT;
+            T *qre = lds + (size_t)r * C::RWS;
+            T *qim = qre + W;
+            if (u == 0) {  // packed: X[0] = re, X[M] = im, both real
+                qre[0] = acc[i].re;
+                qim[0] = T(0);
+                qre[F::pad(M)] = acc[i].im;
+                qim[F::pad(M)] = T(0);
+            } else {
+                const unsigned idx = F::pad(u);
+                qre[idx] = acc[i].re;
+                qim[idx] = acc[i].im;
+            }
         }
     }
     // the Nyquist bin of packed unit 0 (item 0 of the threads with u0 = 0)
