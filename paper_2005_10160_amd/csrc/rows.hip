@@ -459,7 +459,24 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
         const long per_b = (long)nsub * rows;
         const long bq = gr / per_b;
         T *dst = out + bq * out_bstride + (gr - bq * per_b) * (long)nx_out;
-        if (accumulate) {
+        // (x[2j], x[2j+1]) as one vector store where the row allows it: the
+        // lanes' stores then cover whole lines instead of alternate words
+        const bool pairs = (nx_out & 1) == 0 && (reinterpret_cast<size_t>(dst) & (2 * sizeof(T) - 1)) == 0;
+        if (pairs) {
+#pragma unroll
+            for (int sl = 0; sl < PPT; ++sl) {
+                const unsigned j = t + NT * F::elem_out(sl);
+                if (2 * j < (unsigned)nx_out) {
+                    cx<T> *p = reinterpret_cast<cx<T> *>(dst + 2 * j);
+                    cx<T> o{v[sl].re * sc, v[sl].im * sc};
+                    if (accumulate) {
+                        const cx<T> q = *p;
+                        o = cx<T>{q.re + o.re, q.im + o.im};
+                    }
+                    *p = o;
+                }
+            }
+        } else if (accumulate) {
 #pragma unroll
             for (int sl = 0; sl < PPT; ++sl) {
                 const unsigned j = t + NT * F::elem_out(sl);
