@@ -361,9 +361,13 @@ __global__ void __launch_bounds__((RowCfg<T, M>::THREADS))
         off1 = (((long)b * nsrc + tm.s1) * M + u0) * (long)ldc + y;
     }
     const long ustep = (long)NT * ldc;
-    // items gathered per pass over the splits (bounds the registers the
-    // gather holds)
-    constexpr int GH = PPT > 8 ? 8 : PPT;
+    // items gathered per pass over the splits: bounds the registers the
+    // gather holds (FP64 with eight items took 128 registers and spilled
+    // 12-20 bytes a lane, whose scratch stores added up to a fifth to the
+    // written bytes; with four it takes 80: batched 512^2 x 128 adjoint
+    // inverse rows 5.8 -> 5.35 ms, 100-level inverse rows 4.03 -> 3.85 ms)
+    constexpr int GMAX = sizeof(T) == 8 ? 4 : 8;
+    constexpr int GH = PPT > GMAX ? GMAX : PPT;
 #pragma unroll
     for (int h = 0; h < PPT; h += GH) {
         cx<T> acc[GH];
