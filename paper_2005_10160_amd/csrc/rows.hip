@@ -48,9 +48,9 @@ __device__ __forceinline__ Term<T> combo_term(const RowCombo &cmb, int o)
 // Forward rows (a row of Px = 2M points is a transform of M complex points;
 // "points a lane" counts those): 16 points a lane for long rows, real and
 // imaginary parts exchanged one after the other through one LDS array per
-// row.  Rows per
-// workgroup: within 40 KB of LDS and 512 threads, so that two workgroups
-// share a CU and one's loads and stores overlap the other's transforms.
+// row.  Rows per workgroup: within 40 KB of LDS and 512 threads, so that two
+// workgroups share a CU and one's loads and stores overlap the other's
+// transforms.
 // FP32 rows of 1024 points also take 16 points a lane: half a wave per row
 // gives sixteen rows a workgroup, whose transposed stores then cover whole
 // 128-byte lines (8-byte units of 16 consecutive rows; batched 512 x 512 x
