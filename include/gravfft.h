@@ -34,7 +34,10 @@
  *
  * Ownership: a plan owns its device-resident kernel spectra (and, when
  * max_batch > 0, one internal workspace).  The caller owns every data and
- * workspace pointer; all of them are device pointers.  gf_forward and
+ * workspace pointer; all of them are device pointers.  Data pointers must
+ * be aligned to their element size and a caller's workspace to 256 bytes
+ * (every hipMalloc'd or torch-allocated buffer is); otherwise the call
+ * returns GF_EINVAL before anything is enqueued.  gf_forward and
  * gf_adjoint only enqueue kernels on the given HIP stream: they neither
  * allocate nor synchronise, and they return before the result is ready.
  *
@@ -204,7 +207,8 @@ gf_status gf_workspace_bytes(const gf_plan *plan, int op, int batch, size_t *byt
  *              batch), or NULL to use the plan's internal workspace
  *              (needs batch <= max_batch)
  *   hip_stream stream to enqueue on (NULL = default stream)
- * Returns GF_EBUSY when the workspace is too small.
+ * Returns GF_EBUSY when the workspace is too small, GF_EINVAL when a pointer
+ * is misaligned (see Ownership).
  */
 gf_status gf_forward(gf_plan *plan, const void *rho, void *d, int batch, void *workspace,
                      size_t workspace_bytes, void *hip_stream);

@@ -5,6 +5,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -818,9 +819,23 @@ gf_status gf_workspace_bytes(const gf_plan *p, int op, int batch, size_t *bytes)
     return GF_OK;
 }
 
+// Data pointers must be aligned to their element (the kernels take vector
+// accesses only where the pointer allows them); a caller's workspace to 256
+// bytes, as every device allocation is (its slabs are read and written as
+// 16-byte vectors).
+static gf_status check_align(const gf_plan *p, const void *in, const void *out)
+{
+    const uintptr_t e = (uintptr_t)p->elem();
+    if (((uintptr_t)in | (uintptr_t)out) & (e - 1))
+        return fail(GF_EINVAL, "data pointers must be aligned to their %u-byte element", (unsigned)e);
+    return GF_OK;
+}
+
 static gf_status pick_ws(gf_plan *p, int op, int batch, void *&ws, size_t ws_bytes)
 {
     const size_t need = p->ws_bytes(op, batch);
+    if (ws && ((uintptr_t)ws & 255u))
+        return fail(GF_EINVAL, "workspace must be 256-byte aligned");
     if (!ws) {
         if (!p->iws || batch > p->max_batch)
             return fail(GF_EBUSY, "no workspace given and batch %d exceeds the internal workspace (max_batch %d)",
@@ -838,7 +853,9 @@ gf_status gf_forward(gf_plan *p, const void *rho, void *d, int batch, void *work
 {
     if (!p || !rho || !d) return fail(GF_EINVAL, "NULL argument");
     if (batch < 1) return fail(GF_EINVAL, "batch must be >= 1");
-    gf_status s = pick_ws(p, GF_OP_FORWARD, batch, workspace, workspace_bytes);
+    gf_status s = check_align(p, rho, d);
+    if (s != GF_OK) return s;
+    s = pick_ws(p, GF_OP_FORWARD, batch, workspace, workspace_bytes);
     if (s != GF_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     int S, lps;
@@ -978,7 +995,9 @@ gf_status gf_adjoint(gf_plan *p, const void *r, void *g, int batch, void *worksp
 {
     if (!p || !r || !g) return fail(GF_EINVAL, "NULL argument");
     if (batch < 1) return fail(GF_EINVAL, "batch must be >= 1");
-    gf_status s = pick_ws(p, GF_OP_ADJOINT, batch, workspace, workspace_bytes);
+    gf_status s = check_align(p, r, g);
+    if (s != GF_OK) return s;
+    s = pick_ws(p, GF_OP_ADJOINT, batch, workspace, workspace_bytes);
     if (s != GF_OK) return s;
     hipStream_t st = (hipStream_t)hip_stream;
     int S, lps;

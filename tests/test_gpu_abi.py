@@ -254,3 +254,53 @@ def test_resident_storage_against_eq22(gf, nx, ny, nz, prec, mask):
     assert s["resident_bytes"] < 0.3 * s["bttb_bytes"] or min(nx, ny) < 64
     assert s["resident_bytes"] < s["dense_bytes"]
     p.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_alignment(gf, prec):
+    """Inputs and outputs one element into their buffers (aligned to the
+    element, not to a pair of elements) take the row passes' element-wise
+    loads and stores and give the same results bitwise as aligned ones; a
+    caller's workspace off a 256-byte boundary, or a data pointer off its
+    element, is refused with GF_EINVAL and nothing is written."""
+    from paper_2005_10160_amd import _native
+    lib = _native.load()
+    dt = torch.float64 if prec == "f64" else torch.float32
+    g = Geometry(40, 34, 5, 20.0, 25.0, 15.0, 7.0)
+    p = gf.plan(g.nx, g.ny, g.nz, g.dx, g.dy, g.dz, g.h, 0x3F, prec)
+    rho = torch.from_numpy(tiny_density(g.nx, g.ny, g.nz, seed=81, block=None)).to("cuda", dt).unsqueeze(0)
+    want = p.forward(rho)
+    r = torch.randn(want.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(82)).to("cuda", dt)
+    want_g = p.adjoint(r)
+
+    def shifted(shape):
+        n = int(np.prod(shape))
+        return torch.empty(n + 1, dtype=dt, device="cuda")[1:].view(shape)
+
+    rho_u, d_u = shifted(rho.shape), shifted(want.shape)
+    rho_u.copy_(rho)
+    r_u, g_u = shifted(r.shape), shifted(want_g.shape)
+    r_u.copy_(r)
+    p.forward(rho_u, out=d_u)
+    p.adjoint(r_u, out=g_u)
+    torch.cuda.synchronize()
+    assert torch.equal(d_u, want) and torch.equal(g_u, want_g)
+
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    need = p.workspace_bytes("forward", 1)
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    d = torch.zeros_like(want)
+    for off in (8, 128):
+        rc = lib.gf_forward(p._h, vp(rho), vp(d), 1, ctypes.c_void_p(ws.data_ptr() + off), need, st)
+        assert rc == _native.GF_EINVAL, lib.gf_last_error()
+    rc = lib.gf_forward(p._h, ctypes.c_void_p(rho.data_ptr() + 2), vp(d), 1, vp(ws), need, st)
+    assert rc == _native.GF_EINVAL, lib.gf_last_error()
+    rc = lib.gf_adjoint(p._h, vp(r), ctypes.c_void_p(g_u.data_ptr() + 1), 1, vp(ws), ws.numel(), st)
+    assert rc == _native.GF_EINVAL, lib.gf_last_error()
+    torch.cuda.synchronize()
+    assert not d.any()
+    rc = lib.gf_forward(p._h, vp(rho), vp(d), 1, ctypes.c_void_p(ws.data_ptr() + 256), need, st)
+    assert rc == _native.GF_OK, lib.gf_last_error()
+    torch.cuda.synchronize()
+    assert torch.equal(d, want)
+    p.close()
