@@ -98,6 +98,11 @@ struct RowCfgF {
     static constexpr int BPC = TR == TR0 ? 2 : 1;
     static constexpr int WAVES_PER_EU =
         (BPC * THREADS / 256) < 1 ? 1 : ((BPC * THREADS / 256) > 8 ? 8 : BPC * THREADS / 256);
+    static constexpr int LDS_BYTES = TR * ROW_BYTES + TWW * (int)sizeof(T);
+    static_assert(THREADS == TR * NT && THREADS <= 1024, "a row group is TR rows of NT lanes");
+    static_assert(LDS_BYTES <= (TR == TR0 ? 40 : 80) * 1024 + TWW * (int)sizeof(T) && BPC * LDS_BYTES <= 160 * 1024,
+                  "the row groups' LDS fits the workgroups per CU the register target assumes");
+    static_assert(WS % LC == SHIFT % LC && ROW_BYTES % 16 == 0, "row stride: bank shift, 16-byte aligned rows");
 };
 
 // Blocks in XCD-contiguous order: the hardware deals consecutive blocks to
@@ -160,6 +165,15 @@ struct RowCfg {
     // register target: two resident workgroups (512-thread FP64 workgroups
     // need at most 128 registers a lane); larger workgroups fit one
     static constexpr int WAVES_PER_EU = THREADS <= 512 ? 2 * THREADS / 256 : 1;
+    static constexpr int LDS_BYTES = TR * ROW_BYTES + TWW * (int)sizeof(T);
+    static_assert(THREADS == TR * NT && THREADS <= 1024, "a row group is TR rows of NT lanes");
+    static_assert(THREADS > 512 || 2 * LDS_BYTES <= 160 * 1024,
+                  "two workgroups of at most 512 threads share a CU's LDS");
+    static_assert(RWS % (128 / (int)sizeof(T)) ==
+                      ((128 / (int)sizeof(T)) / TR > 16 / (int)sizeof(T) ? (128 / (int)sizeof(T)) / TR
+                                                                       : 16 / (int)sizeof(T)) % (128 / (int)sizeof(T)) &&
+                      ROW_BYTES % 16 == 0,
+                  "row stride: bank shift, 16-byte aligned rows");
 };
 
 template <typename T, int M, bool HALF>
